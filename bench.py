@@ -1,0 +1,211 @@
+"""Benchmark of the multi-word NTT / modular BLAS hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (one step, the paper-scale plain configuration): forward and inverse
+negacyclic NTT at N = 2^16 over a 124-bit prime q = 1 mod 2^18 (coefficients
+uniform in [0, q), two 64-bit limbs), then vec_mulmod, vec_addmod and
+vec_axpymod on length-2^16 vectors, one library call per operation.  Inputs are
+seeded synthetic data already resident in device memory.
+
+Prints one JSON line.  ``value`` is 124-bit NTTs per second of the whole step
+(2 transforms per step).  Extra fields: per-op latency p50/p99 (HIP events on
+the op's stream), algorithmic Gmulmod/s, the batched (many transforms per
+call) rate, the roofline of the dominant kernel call and the CPU oracle's
+rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X peaks (published): HBM3E 8 TB/s; 256 CUs x 4 SIMD16 x 2.4 GHz = 39.3 T
+# 32-bit integer VALU lane-ops/s.
+HBM_PEAK_GBS = 8000.0
+INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# Algorithmic 32-bit word operations per butterfly (schoolbook Shoup mul-mod
+# with W words: quotient estimate from the W(W+1)/2 top-column partial
+# products, W(W+1)/2 each for the low halves of x*w and Q*q, W word subs for
+# the remainder, and 2W word add/sub for the butterfly's sum and difference).
+def butterfly_word_ops(W):
+    return 3 * (W * (W + 1) // 2) + W + 2 * W
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * p / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """The oracle (plain Python integers, one core) on a bounded sample of the
+    same workload: forward-NTT outputs of the 2^16-point polynomial computed one
+    by one from the definition, scaled to whole transforms per second."""
+    import oracle
+    from paper_2509_12494_amd import workloads as W
+    a = W.to_ints(wl.data["poly"])
+    n = len(a)
+    t0 = time.perf_counter()
+    done = 0
+    k = 0
+    while time.perf_counter() - t0 < budget_s:
+        oracle.ntt.forward_at(a, wl.q, [k])
+        done += 1
+        k = (k * 7919 + 1) % n
+    dt = time.perf_counter() - t0
+    per_output = dt / done
+    return {"value": 1.0 / (per_output * n), "unit": "NTT/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} forward outputs A_k of one N=2^16 124-bit transform, each an O(N) sum "
+                      f"from the definition ({dt:.1f} s), scaled to N outputs per transform"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=96, help="transforms per call in the batched leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; runs on more than one GPU are not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_12494_amd import mwntt
+    from paper_2509_12494_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = W.config_paper(124)
+    q, limbs, log2n = wl.q, wl.limbs, wl.log2n
+    n = 1 << log2n
+    plan = mwntt.ntt_plan(log2n, q, limbs)
+    poly = mwntt.to_device(wl.data["poly"])
+    spec = torch.empty_like(poly)
+    back = torch.empty_like(poly)
+    xa = mwntt.to_device(wl.data["a"])
+    xb = mwntt.to_device(wl.data["b"])
+    c_mul = torch.empty_like(xa)
+    c_add = torch.empty_like(xa)
+    y = xb.clone()
+    alpha = wl.data["alpha"]
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+
+    ops = {
+        "ntt_forward": lambda: plan.forward(spec, poly, batch=1, stream=sp),
+        "ntt_inverse": lambda: plan.inverse(back, spec, batch=1, stream=sp),
+        "vec_mulmod": lambda: mwntt.vec_mulmod(c_mul, xa, xb, q, limbs, stream=sp),
+        "vec_addmod": lambda: mwntt.vec_addmod(c_add, xa, xb, q, limbs, stream=sp),
+        "vec_axpymod": lambda: mwntt.vec_axpymod(y, alpha, xa, q, limbs, stream=sp),
+    }
+
+    def step():
+        for f in ops.values():
+            f()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / args.steps
+
+    # correctness of the timed outputs: the inverse undid the forward
+    assert torch.equal(back, poly), "round trip failed"
+
+    # per-op latency, each op bracketed by events on its stream (paper protocol:
+    # mean of the last half of the runs; here also p50 / p99)
+    lat = {}
+    for name, f in ops.items():
+        reps = 200
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            f()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        us = [e0.elapsed_time(e1) * 1e3 for e0, e1 in evs]
+        half = us[reps // 2:]
+        lat[name] = {"p50_us": round(percentile(us, 50), 3), "p99_us": round(percentile(us, 99), 3),
+                     "mean_last_half_us": round(sum(half) / len(half), 3)}
+
+    # batched leg: many 2^16 transforms in one call (same plan, same q)
+    B = args.batch
+    bpoly = mwntt.to_device(W.uniform_residues(W.rng(2100), q, n * B, limbs))
+    bspec = torch.empty_like(bpoly)
+    for _ in range(3):
+        plan.forward(bspec, bpoly, batch=B, stream=sp)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.forward(bspec, bpoly, batch=B, stream=sp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched_us = e0.elapsed_time(e1) * 1e3 / reps
+    batched_ntt_s = B / (batched_us * 1e-6)
+
+    # roofline of the dominant call: the batched forward transform (two kernels:
+    # column pass + row pass), ALU-bound
+    W_words = 2 * limbs
+    bfly = (n // 2) * log2n
+    ops_per_call = B * bfly * butterfly_word_ops(W_words)
+    achieved_tops = ops_per_call / (batched_us * 1e-6) / 1e12
+
+    mulmods_step = 2 * bfly + 2 * n        # two transforms + vec_mulmod + vec_axpymod
+    res = {
+        "metric": "128-bit NTT/s at N=2^16 (batched vs plain), Gmulmod/s, p50/p99 latency",
+        "value": round(2.0 / (ms_per_step * 1e-3), 2),
+        "unit": "NTT/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u128 (2x64-bit limbs, 124-bit prime)",
+        "data": "synthetic (seeded uniform residues)",
+        "config": {"workload": "plain, paper scale: forward+inverse negacyclic NTT N=2^16, 124-bit q=1 mod 2^18; "
+                               "vec_mulmod/addmod/axpymod n=2^16; one launch per op",
+                   "N": n, "q_bits": q.bit_length(), "limbs": limbs, "split_log_n1": plan.split},
+        "gmulmod_s": round(mulmods_step / (ms_per_step * 1e-3) / 1e9, 4),
+        "latency_us": lat,
+        "batched": {"batch": B, "us_per_call": round(batched_us, 2), "ntt_s": round(batched_ntt_s, 1),
+                    "speedup_vs_plain_forward": round(batched_ntt_s / (1e6 / lat["ntt_forward"]["p50_us"]), 2),
+                    "gmulmod_s": round(B * bfly / (batched_us * 1e-6) / 1e9, 3)},
+        "roofline": {"bound": "alu", "kernel": "ntt_forward batched (column + row pass kernels)",
+                     "achieved": round(achieved_tops, 3), "peak": round(INT32_PEAK_TOPS, 2),
+                     "unit": "Tint32op/s", "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": None,
+                     "ops_per_butterfly": butterfly_word_ops(W_words)},
+        "wall_s_timed_region": round(wall, 4),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(wl)
+    plan.destroy()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

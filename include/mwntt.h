@@ -1,0 +1,142 @@
+/*
+ * mwntt.h -- C ABI of the multi-word modular NTT / BLAS library for MI355X (gfx950).
+ *
+ * Operations (arXiv 2509.12494, "Towards Closing the Performance Gap for
+ * Cryptographic Kernels Between CPUs and Specialized Hardware"):
+ *   - modular add / sub / mul over Z_q (Background, modular arithmetic,
+ *     Eq. saddmod, Eq. ssubmod, Eq. barrett);
+ *   - point-wise polynomial operations as BLAS: vector add, vector sub,
+ *     point-wise vector multiply and axpy y = a*x + y (Background, polynomial
+ *     operations);
+ *   - the number theoretic transform of Eq. (ntt), in its negacyclic form over
+ *     Z_q[X]/(X^N + 1), and its inverse (Background, polynomial multiplication
+ *     using NTT).
+ * Moduli are "double-word" (two 64-bit words, q < 2^124, the largest width the
+ * paper's Barrett reduction allows for 128-bit arithmetic) or single-word
+ * (q < 2^60, the same rule for one 64-bit word).
+ *
+ * Data layout.  A residue is `limbs` little-endian uint64_t words (word 0 is
+ * the least significant; the paper's notation [x0, x1] lists the high word
+ * first, which is notation only).  A vector of n residues is n*limbs words,
+ * element-major ([n][limbs]); a batch of polynomials is [batch][N][limbs].
+ * All device pointers must be aligned to 8*limbs bytes.
+ *
+ * Values.  Every input residue must be canonical, 0 <= x < q (the paper's
+ * assumption for Eq. saddmod / ssubmod); results for non-canonical inputs are
+ * unspecified.  Every output is canonical.
+ *
+ * Moduli.  `q` points to `limbs` host words.  limbs == 1: 33 <= bitlen(q) <= 60
+ * for vec_mulmod, 2 <= bitlen(q) <= 60 otherwise.  limbs == 2:
+ * 97 <= bitlen(q) <= 124 for vec_mulmod, 61 <= bitlen(q) <= 124 otherwise.
+ * q must be odd.  Primality is the caller's responsibility (an NTT plan checks
+ * that its root has order exactly 2N).
+ *
+ * Streams and errors.  `stream` is a hipStream_t (NULL = the null stream).
+ * Argument errors return a negative status synchronously and enqueue nothing.
+ * Kernels run asynchronously on the stream; a launch failure is reported as
+ * MW_EDEVICE.  Functions never synchronize the device unless stated.
+ *
+ * Ownership.  The caller allocates and frees every data buffer.  A plan owns
+ * its device tables and scratch and frees them in ntt_plan_destroy.
+ */
+#ifndef MWNTT_H
+#define MWNTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum mw_status {
+  MW_OK = 0,
+  MW_EINVAL = -1,    /* null pointer, zero/oversized length, bad flag */
+  MW_EMODULUS = -2,  /* modulus width/parity/congruence not supported */
+  MW_ESIZE = -3,     /* transform length outside 2^1 .. 2^17 */
+  MW_ENOMEM = -4,    /* device or host allocation failed */
+  MW_EDEVICE = -5,   /* HIP runtime error (launch failure, no device) */
+  MW_EROOT = -6      /* supplied root is not a primitive 2N-th root */
+};
+
+/* Returns a static string describing a status code. */
+const char* mw_status_str(int status);
+
+/* ------------------------------------------------------------------------ */
+/* Element-wise modular BLAS (Background, polynomial operations as BLAS).    */
+/* c[i] = (a[i] + b[i]) mod q, etc., for 0 <= i < n.  n == 0 is a no-op.     */
+/* Outputs may alias inputs exactly (c == a or c == b); partial overlap is   */
+/* undefined.                                                                */
+/* ------------------------------------------------------------------------ */
+int vec_addmod(void* d_c, const void* d_a, const void* d_b, size_t n,
+               const uint64_t* q, uint32_t limbs, void* stream);
+int vec_submod(void* d_c, const void* d_a, const void* d_b, size_t n,
+               const uint64_t* q, uint32_t limbs, void* stream);
+/* Point-wise product reduced with Barrett's method (Eq. barrett). */
+int vec_mulmod(void* d_c, const void* d_a, const void* d_b, size_t n,
+               const uint64_t* q, uint32_t limbs, void* stream);
+/* y[i] = (alpha * x[i] + y[i]) mod q; alpha is `limbs` host words, < q. */
+int vec_axpymod(void* d_y, const uint64_t* alpha, const void* d_x, size_t n,
+                const uint64_t* q, uint32_t limbs, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Negacyclic NTT over Z_q[X]/(X^N + 1), N = 2^log2n, 1 <= log2n <= 17.     */
+/*   forward: A[k] = sum_j a[j] psi^(j(2k+1)) mod q   (natural order)        */
+/*   inverse: a[j] = N^-1 psi^-j sum_k A[k] psi^(-2jk) mod q                 */
+/* i.e. Eq. (ntt) on the psi-twisted input with omega_N = psi^2.  psi is a   */
+/* primitive 2N-th root of unity: the caller's, or by default the smallest   */
+/* one in [1, q).  q must satisfy q = 1 (mod 2N).                            */
+/* ------------------------------------------------------------------------ */
+typedef struct ntt_plan_s* ntt_plan_t;
+
+/* ntt_forward writes its output in bit-reversed order (A[bitrev(i)] at i).  */
+#define NTT_BITREV_OUT 0x1u
+/* ntt_inverse reads its input in bit-reversed order.                        */
+#define NTT_BITREV_IN 0x2u
+
+/* Creates a plan on the current HIP device: builds the twiddle tables
+ * (psi^bitrev(i) and psi^-bitrev(i) with their Shoup companions) on the host
+ * and copies them to device memory, and allocates a scratch buffer for the
+ * two-pass transforms.  psi may be NULL (canonical root) or point to `limbs`
+ * host words.  flags: 0 or a combination of NTT_BITREV_OUT / NTT_BITREV_IN.
+ * Synchronous. */
+int ntt_plan(ntt_plan_t* plan, uint32_t log2n, const uint64_t* q, uint32_t limbs,
+             const uint64_t* psi, uint32_t flags);
+/* Frees the plan's device memory (synchronizes the device first). */
+int ntt_plan_destroy(ntt_plan_t plan);
+/* The root psi the plan uses (limbs words written to psi_out). */
+int ntt_plan_root(ntt_plan_t plan, uint64_t* psi_out);
+
+/* Decomposition of the transform (used by the autotuner and by tests):
+ * log_n1 == 0 runs each transform in one workgroup (N <= 2^12 for two-word
+ * moduli, N <= 2^13 for one-word moduli); otherwise two passes over device
+ * memory with N1 = 2^log_n1 rows and N2 = N / N1 columns, 3 <= log2(N1),
+ * log2(N2) <= 9.  Results do not depend on the split.  Not thread-safe with
+ * concurrent transforms on the same plan. */
+int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1);
+int ntt_plan_get_split(ntt_plan_t plan, uint32_t* log_n1);
+
+/* Transforms `batch` polynomials [batch][N][limbs].  d_out == d_in is
+ * allowed.  Calls on one plan must not overlap in time on different streams
+ * (they share the plan's scratch buffer); plans are independent. */
+int ntt_forward(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, void* stream);
+int ntt_inverse(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Host-only helpers (no device needed): the plan's own arithmetic, exposed */
+/* for inspection.                                                           */
+/* ------------------------------------------------------------------------ */
+/* Smallest primitive 2N-th root of unity modulo q (N = 2^log2n). */
+int mw_canonical_root(const uint64_t* q, uint32_t limbs, uint32_t log2n, uint64_t* psi_out);
+/* Shoup companion floor(w * 2^(64*limbs) / q) of a constant w < q. */
+int mw_shoup_companion(const uint64_t* w, const uint64_t* q, uint32_t limbs, uint64_t* out);
+/* Barrett constant floor(2^(2b) / q), b = bitlen(q) (b+1 bits, limbs words). */
+int mw_barrett_mu(const uint64_t* q, uint32_t limbs, uint64_t* out);
+/* Library version string. */
+const char* mw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MWNTT_H */

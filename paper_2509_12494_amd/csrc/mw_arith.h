@@ -1,0 +1,452 @@
+// Multi-word modular arithmetic for gfx950 (CDNA4) vector lanes.
+//
+// A residue of an l-bit modulus is held in W little-endian 32-bit words per
+// lane: W = 2 for q < 2^60 (one 64-bit limb), W = 4 for q < 2^124 (two 64-bit
+// limbs).  The paper's double-word arithmetic (Background, double-word
+// arithmetic: add with carry, sub with borrow, the schoolbook product of
+// Eq. muls) maps onto CDNA4 vector instructions as follows:
+//   * word product      -> v_mad_u64_u32 (32x32+64 -> 64, with carry-out mask)
+//   * add with carry    -> v_add_co_u32 / v_addc_co_u32 (carry in a lane mask)
+//   * sub with borrow   -> v_sub_co_u32 / v_subb_co_u32
+//   * masked select     -> v_cndmask_b32 on the borrow mask
+// which is the per-lane carry support the paper's MQX extension proposes for
+// AVX-512 (Table tab:mqx).  On gfx950 the 32-bit multiplies issue at the same
+// rate as the carry adds, so the cost of a mul-mod is its instruction count.
+//
+// Reductions:
+//   * Shoup multiplication by a constant w with precomputed
+//     w' = floor(w * 2^(32W) / q) (twiddle factors, the axpy scalar).  The
+//     quotient estimate uses only the partial products of columns >= W-1 of
+//     x*w' (columns 0..W-2 are dropped), which under-estimates the exact Shoup
+//     quotient by at most 4 (W=4) or 1 (W=2); the result x*w - Q*q is then in
+//     [0, 6q) for any x < 2^(32W).
+//   * Barrett reduction (Background, modular arithmetic, Eq. barrett) for a
+//     product of two variables, with k = 2*bitlen(q): mu = floor(2^(2b)/q),
+//     q1 = floor(x / 2^(b-1)), q3 = floor(q1*mu / 2^(b+1)), r = x - q3*q.
+//     q3 is at most 2 below floor(x/q) (plus 1 for the dropped low columns of
+//     q1*mu with W=4), so r < 4q and two conditional subtractions make it
+//     canonical.
+//
+// Everything here is device code; host-side constants (w', mu) are produced by
+// the plan code with exact long division.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mw {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+template <int W>
+struct Res {
+  u32 v[W];
+};
+
+// Per-modulus constants, passed by value as a kernel argument (uniform).
+template <int W>
+struct Modulus {
+  u32 q[W];
+  u32 q2[W];   // 2q
+  u32 q4[W];   // 4q
+  u32 q8[W];   // 8q
+  u32 mu[W];   // Barrett mu = floor(2^(2b)/q) (b+1 bits)
+  u32 bits;    // b = bitlen(q)
+  u32 pad_[3];
+};
+
+// ---------------------------------------------------------------------------
+// word-level primitives
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
+__device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
+__device__ __forceinline__ u64 pack(u32 lo, u32 hi) { return ((u64)hi << 32) | lo; }
+
+// acc = a*b + acc (mod 2^64); returns the carry-out lane mask.
+__device__ __forceinline__ u64 mad_cc(u32 a, u32 b, u64& acc) {
+  u64 cc;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc), "=s"(cc) : "v"(a), "v"(b));
+  return cc;
+}
+
+// x + carry(cc) where cc is a lane mask produced by a carry-out.
+__device__ __forceinline__ u32 add_carry(u32 x, u64 cc) {
+  u32 d;
+  u64 co;
+  asm("v_addc_co_u32 %0, %1, %2, 0, %3" : "=v"(d), "=s"(co) : "v"(x), "s"(cc));
+  return d;
+}
+
+// plain a*b + c, no carry needed (caller guarantees no overflow, or only
+// the result modulo 2^64 is used)
+__device__ __forceinline__ u64 mad(u32 a, u32 b, u64 c) { return (u64)a * b + c; }
+
+// ---------------------------------------------------------------------------
+// multi-word add / sub / compare-select
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ Res<W> add(const Res<W>& a, const Res<W>& b) {
+  Res<W> r;
+  u32 c = 0;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r.v[i] = __builtin_addc(a.v[i], b.v[i], c, &c);
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ Res<W> add(const Res<W>& a, const u32 (&b)[W]) {
+  Res<W> r;
+  u32 c = 0;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r.v[i] = __builtin_addc(a.v[i], b[i], c, &c);
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ Res<W> sub(const Res<W>& a, const Res<W>& b, u32& borrow) {
+  Res<W> r;
+  u32 c = 0;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r.v[i] = __builtin_subc(a.v[i], b.v[i], c, &c);
+  borrow = c;
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ Res<W> sub(const Res<W>& a, const u32 (&b)[W], u32& borrow) {
+  Res<W> r;
+  u32 c = 0;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r.v[i] = __builtin_subc(a.v[i], b[i], c, &c);
+  borrow = c;
+  return r;
+}
+
+// a >= m ? a - m : a   (Eq. saddmod's conditional subtraction)
+template <int W>
+__device__ __forceinline__ Res<W> csub(const Res<W>& a, const u32 (&m)[W]) {
+  u32 borrow;
+  Res<W> d = sub(a, m, borrow);
+  Res<W> r;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r.v[i] = borrow ? a.v[i] : d.v[i];
+  return r;
+}
+
+// canonical (a + b) mod q for a, b in [0, q)   (Eq. saddmod)
+template <int W>
+__device__ __forceinline__ Res<W> addmod(const Res<W>& a, const Res<W>& b, const Modulus<W>& M) {
+  return csub(add(a, b), M.q);
+}
+
+// canonical (a - b) mod q for a, b in [0, q)   (Eq. ssubmod)
+template <int W>
+__device__ __forceinline__ Res<W> submod(const Res<W>& a, const Res<W>& b, const Modulus<W>& M) {
+  u32 borrow;
+  Res<W> d = sub(a, b, borrow);
+  Res<W> e = add(d, M.q);
+  Res<W> r;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r.v[i] = borrow ? e.v[i] : d.v[i];
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// products
+// ---------------------------------------------------------------------------
+
+// low W words of a*b
+__device__ __forceinline__ Res<4> mul_lo(const Res<4>& a, const u32 (&b)[4]) {
+  Res<4> r;
+  u64 c0 = (u64)a.v[0] * b[0];
+  r.v[0] = lo32(c0);
+  u64 c1 = mad(a.v[0], b[1], (u64)hi32(c0));          // < 2^64, no carry
+  u64 cc = mad_cc(a.v[1], b[0], c1);
+  r.v[1] = lo32(c1);
+  u64 c2 = pack(hi32(c1), add_carry(0u, cc));         // carry from column 1
+  c2 = mad(a.v[0], b[2], c2);                         // column 2 modulo 2^64:
+  c2 = mad(a.v[1], b[1], c2);                         // only its low 64 bits reach
+  c2 = mad(a.v[2], b[0], c2);                         // words 2 and 3
+  r.v[2] = lo32(c2);
+  u64 c3 = (u64)hi32(c2);
+  c3 = mad(a.v[0], b[3], c3);                         // column 3: low word only
+  c3 = mad(a.v[1], b[2], c3);
+  c3 = mad(a.v[2], b[1], c3);
+  c3 = mad(a.v[3], b[0], c3);
+  r.v[3] = lo32(c3);
+  return r;
+}
+
+__device__ __forceinline__ Res<2> mul_lo(const Res<2>& a, const u32 (&b)[2]) {
+  Res<2> r;
+  u64 c0 = (u64)a.v[0] * b[0];
+  r.v[0] = lo32(c0);
+  u64 c1 = (u64)hi32(c0);
+  c1 = mad(a.v[0], b[1], c1);
+  c1 = mad(a.v[1], b[0], c1);
+  r.v[1] = lo32(c1);
+  return r;
+}
+
+// Shoup quotient estimate: floor(sum over columns >= W-1 of x*ws / 2^(32W)).
+// Under-estimates floor(x*ws / 2^(32W)) by at most 4 (W=4) / 1 (W=2).
+__device__ __forceinline__ Res<4> mul_hi_est(const Res<4>& x, const u32 (&ws)[4]) {
+  Res<4> Q;
+  // column 3
+  u64 acc = (u64)x.v[0] * ws[3];
+  u64 cc = mad_cc(x.v[1], ws[2], acc);
+  u32 t = add_carry(0u, cc);
+  cc = mad_cc(x.v[2], ws[1], acc);
+  t = add_carry(t, cc);
+  cc = mad_cc(x.v[3], ws[0], acc);
+  t = add_carry(t, cc);
+  // column 4
+  acc = pack(hi32(acc), t);
+  cc = mad_cc(x.v[1], ws[3], acc);
+  t = add_carry(0u, cc);
+  cc = mad_cc(x.v[2], ws[2], acc);
+  t = add_carry(t, cc);
+  cc = mad_cc(x.v[3], ws[1], acc);
+  t = add_carry(t, cc);
+  Q.v[0] = lo32(acc);
+  // column 5
+  acc = pack(hi32(acc), t);
+  cc = mad_cc(x.v[2], ws[3], acc);
+  t = add_carry(0u, cc);
+  cc = mad_cc(x.v[3], ws[2], acc);
+  t = add_carry(t, cc);
+  Q.v[1] = lo32(acc);
+  // column 6 (+7): the estimate is below 2^128, so no carry leaves it
+  acc = pack(hi32(acc), t);
+  acc = mad(x.v[3], ws[3], acc);
+  Q.v[2] = lo32(acc);
+  Q.v[3] = hi32(acc);
+  return Q;
+}
+
+__device__ __forceinline__ Res<2> mul_hi_est(const Res<2>& x, const u32 (&ws)[2]) {
+  Res<2> Q;
+  u64 acc = (u64)x.v[0] * ws[1];                      // column 1
+  u64 cc = mad_cc(x.v[1], ws[0], acc);
+  u32 t = add_carry(0u, cc);
+  acc = pack(hi32(acc), t);                           // column 2 (+3)
+  acc = mad(x.v[1], ws[1], acc);
+  Q.v[0] = lo32(acc);
+  Q.v[1] = hi32(acc);
+  return Q;
+}
+
+// Full 2W-word product a*b.
+__device__ __forceinline__ void mul_full(const Res<4>& a, const Res<4>& b, u32 (&r)[8]) {
+  u64 acc = (u64)a.v[0] * b.v[0];
+  r[0] = lo32(acc);
+  // column 1
+  acc = (u64)hi32(acc);
+  acc = mad(a.v[0], b.v[1], acc);
+  u64 cc = mad_cc(a.v[1], b.v[0], acc);
+  u32 t = add_carry(0u, cc);
+  r[1] = lo32(acc);
+  // column 2
+  acc = pack(hi32(acc), t);
+  cc = mad_cc(a.v[0], b.v[2], acc);
+  t = add_carry(0u, cc);
+  cc = mad_cc(a.v[1], b.v[1], acc);
+  t = add_carry(t, cc);
+  cc = mad_cc(a.v[2], b.v[0], acc);
+  t = add_carry(t, cc);
+  r[2] = lo32(acc);
+  // column 3
+  acc = pack(hi32(acc), t);
+  cc = mad_cc(a.v[0], b.v[3], acc);
+  t = add_carry(0u, cc);
+  cc = mad_cc(a.v[1], b.v[2], acc);
+  t = add_carry(t, cc);
+  cc = mad_cc(a.v[2], b.v[1], acc);
+  t = add_carry(t, cc);
+  cc = mad_cc(a.v[3], b.v[0], acc);
+  t = add_carry(t, cc);
+  r[3] = lo32(acc);
+  // column 4
+  acc = pack(hi32(acc), t);
+  cc = mad_cc(a.v[1], b.v[3], acc);
+  t = add_carry(0u, cc);
+  cc = mad_cc(a.v[2], b.v[2], acc);
+  t = add_carry(t, cc);
+  cc = mad_cc(a.v[3], b.v[1], acc);
+  t = add_carry(t, cc);
+  r[4] = lo32(acc);
+  // column 5
+  acc = pack(hi32(acc), t);
+  cc = mad_cc(a.v[2], b.v[3], acc);
+  t = add_carry(0u, cc);
+  cc = mad_cc(a.v[3], b.v[2], acc);
+  t = add_carry(t, cc);
+  r[5] = lo32(acc);
+  // column 6 (+7)
+  acc = pack(hi32(acc), t);
+  acc = mad(a.v[3], b.v[3], acc);
+  r[6] = lo32(acc);
+  r[7] = hi32(acc);
+}
+
+__device__ __forceinline__ void mul_full(const Res<2>& a, const Res<2>& b, u32 (&r)[4]) {
+  u64 acc = (u64)a.v[0] * b.v[0];
+  r[0] = lo32(acc);
+  acc = (u64)hi32(acc);
+  acc = mad(a.v[0], b.v[1], acc);
+  u64 cc = mad_cc(a.v[1], b.v[0], acc);
+  u32 t = add_carry(0u, cc);
+  r[1] = lo32(acc);
+  acc = pack(hi32(acc), t);
+  acc = mad(a.v[1], b.v[1], acc);
+  r[2] = lo32(acc);
+  r[3] = hi32(acc);
+}
+
+// ---------------------------------------------------------------------------
+// modular multiplication
+// ---------------------------------------------------------------------------
+
+// Shoup: x*w mod q up to a multiple of q, result in [0, 6q), for x < 2^(32W),
+// w < q, ws = floor(w * 2^(32W) / q).
+template <int W>
+__device__ __forceinline__ Res<W> shoup_mul(const Res<W>& x, const u32 (&w)[W], const u32 (&ws)[W],
+                                            const Modulus<W>& M) {
+  Res<W> Q = mul_hi_est(x, ws);
+  Res<W> xw = mul_lo(x, w);
+  Res<W> qq = mul_lo(Q, M.q);
+  u32 b;
+  return sub(xw, qq, b);
+}
+
+// funnel shift: bits [s, s+32) of the 64-bit value hi:lo, 0 <= s < 32
+__device__ __forceinline__ u32 funnel(u32 hi, u32 lo, u32 s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
+
+// Barrett: canonical a*b mod q for a, b in [0, q).  W=4 requires
+// 97 <= bitlen(q) <= 124, W=2 requires 33 <= bitlen(q) <= 60.
+__device__ __forceinline__ Res<4> barrett_mul(const Res<4>& a, const Res<4>& b, const Modulus<4>& M) {
+  u32 x[8];
+  mul_full(a, b, x);
+  // q1 = x >> (b-1), b-1 in [96, 123]: word offset 3
+  const u32 s1 = (M.bits - 1) & 31;
+  Res<4> q1;
+  q1.v[0] = funnel(x[4], x[3], s1);
+  q1.v[1] = funnel(x[5], x[4], s1);
+  q1.v[2] = funnel(x[6], x[5], s1);
+  q1.v[3] = funnel(x[7], x[6], s1);
+  // q2 = q1 * mu, columns >= 2 (dropped part < 2^98 <= 2^(b+1))
+  u32 q2[8];
+  {
+    const u32* m = M.mu;
+    u64 acc = (u64)q1.v[0] * m[2];
+    u64 cc = mad_cc(q1.v[1], m[1], acc);
+    u32 t = add_carry(0u, cc);
+    cc = mad_cc(q1.v[2], m[0], acc);
+    t = add_carry(t, cc);
+    q2[2] = lo32(acc);
+    acc = pack(hi32(acc), t);
+    cc = mad_cc(q1.v[0], m[3], acc);
+    t = add_carry(0u, cc);
+    cc = mad_cc(q1.v[1], m[2], acc);
+    t = add_carry(t, cc);
+    cc = mad_cc(q1.v[2], m[1], acc);
+    t = add_carry(t, cc);
+    cc = mad_cc(q1.v[3], m[0], acc);
+    t = add_carry(t, cc);
+    q2[3] = lo32(acc);
+    acc = pack(hi32(acc), t);
+    cc = mad_cc(q1.v[1], m[3], acc);
+    t = add_carry(0u, cc);
+    cc = mad_cc(q1.v[2], m[2], acc);
+    t = add_carry(t, cc);
+    cc = mad_cc(q1.v[3], m[1], acc);
+    t = add_carry(t, cc);
+    q2[4] = lo32(acc);
+    acc = pack(hi32(acc), t);
+    cc = mad_cc(q1.v[2], m[3], acc);
+    t = add_carry(0u, cc);
+    cc = mad_cc(q1.v[3], m[2], acc);
+    t = add_carry(t, cc);
+    q2[5] = lo32(acc);
+    acc = pack(hi32(acc), t);
+    acc = mad(q1.v[3], m[3], acc);
+    q2[6] = lo32(acc);
+    q2[7] = hi32(acc);
+  }
+  // q3 = q2 >> (b+1), b+1 in [98, 125]: word offset 3
+  const u32 s3 = (M.bits + 1) & 31;
+  Res<4> q3;
+  q3.v[0] = funnel(q2[4], q2[3], s3);
+  q3.v[1] = funnel(q2[5], q2[4], s3);
+  q3.v[2] = funnel(q2[6], q2[5], s3);
+  q3.v[3] = funnel(q2[7], q2[6], s3);
+  // r = x - q3*q  (mod 2^128; the true value is in [0, 4q))
+  Res<4> xl;
+  xl.v[0] = x[0]; xl.v[1] = x[1]; xl.v[2] = x[2]; xl.v[3] = x[3];
+  Res<4> qq = mul_lo(q3, M.q);
+  u32 bo;
+  Res<4> r = sub(xl, qq, bo);
+  r = csub(r, M.q2);
+  return csub(r, M.q);
+}
+
+__device__ __forceinline__ Res<2> barrett_mul(const Res<2>& a, const Res<2>& b, const Modulus<2>& M) {
+  u32 x[4];
+  mul_full(a, b, x);
+  // q1 = x >> (b-1), b-1 in [32, 59]: word offset 1
+  const u32 s1 = (M.bits - 1) & 31;
+  Res<2> q1;
+  q1.v[0] = funnel(x[2], x[1], s1);
+  q1.v[1] = funnel(x[3], x[2], s1);
+  Res<2> mu;
+  mu.v[0] = M.mu[0];
+  mu.v[1] = M.mu[1];
+  u32 q2[4];
+  mul_full(q1, mu, q2);
+  // q3 = q2 >> (b+1), b+1 in [34, 61]: word offset 1
+  const u32 s3 = (M.bits + 1) & 31;
+  Res<2> q3;
+  q3.v[0] = funnel(q2[2], q2[1], s3);
+  q3.v[1] = funnel(q2[3], q2[2], s3);
+  Res<2> xl;
+  xl.v[0] = x[0]; xl.v[1] = x[1];
+  Res<2> qq = mul_lo(q3, M.q);
+  u32 bo;
+  Res<2> r = sub(xl, qq, bo);
+  r = csub(r, M.q2);
+  return csub(r, M.q);
+}
+
+// ---------------------------------------------------------------------------
+// loads / stores of one residue (W words, 16-byte or 8-byte aligned)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Res<4> load_res(const void* p) {
+  uint4 v = *reinterpret_cast<const uint4*>(p);
+  Res<4> r;
+  r.v[0] = v.x; r.v[1] = v.y; r.v[2] = v.z; r.v[3] = v.w;
+  return r;
+}
+__device__ __forceinline__ void store_res(void* p, const Res<4>& r) {
+  *reinterpret_cast<uint4*>(p) = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+}
+__device__ __forceinline__ Res<2> load_res2(const void* p) {
+  uint2 v = *reinterpret_cast<const uint2*>(p);
+  Res<2> r;
+  r.v[0] = v.x; r.v[1] = v.y;
+  return r;
+}
+__device__ __forceinline__ void store_res2(void* p, const Res<2>& r) {
+  *reinterpret_cast<uint2*>(p) = make_uint2(r.v[0], r.v[1]);
+}
+
+template <int W> struct ResIO;
+template <> struct ResIO<4> {
+  __device__ static __forceinline__ Res<4> load(const void* p) { return load_res(p); }
+  __device__ static __forceinline__ void store(void* p, const Res<4>& r) { store_res(p, r); }
+};
+template <> struct ResIO<2> {
+  __device__ static __forceinline__ Res<2> load(const void* p) { return load_res2(p); }
+  __device__ static __forceinline__ void store(void* p, const Res<2>& r) { store_res2(p, r); }
+};
+
+}  // namespace mw

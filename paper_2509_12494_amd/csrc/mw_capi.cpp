@@ -1,0 +1,55 @@
+// C ABI: status strings and the host-only helpers (the plan's own arithmetic).
+#include <stdint.h>
+
+#include "../../include/mwntt.h"
+#include "mw_host_math.h"
+
+extern "C" const char* mw_status_str(int status) {
+  switch (status) {
+    case MW_OK: return "ok";
+    case MW_EINVAL: return "invalid argument";
+    case MW_EMODULUS: return "unsupported modulus";
+    case MW_ESIZE: return "unsupported transform length";
+    case MW_ENOMEM: return "out of memory";
+    case MW_EDEVICE: return "HIP device error";
+    case MW_EROOT: return "not a primitive 2N-th root of unity";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* mw_version(void) { return "mwntt 0.1 (gfx950)"; }
+
+static bool width_ok(mwhost::u128 q, uint32_t limbs) {
+  if (limbs != 1 && limbs != 2) return false;
+  int b = mwhost::bitlen(q);
+  return (q & 1) && q >= 3 && b <= (limbs == 1 ? 60 : 124);
+}
+
+extern "C" int mw_canonical_root(const uint64_t* q, uint32_t limbs, uint32_t log2n, uint64_t* psi_out) {
+  if (!q || !psi_out || (limbs != 1 && limbs != 2)) return MW_EINVAL;
+  if (log2n < 1 || log2n > 17) return MW_ESIZE;
+  mwhost::u128 Q = mwhost::from_words(q, limbs);
+  if (!width_ok(Q, limbs)) return MW_EMODULUS;
+  if ((Q - 1) % ((mwhost::u128)2 << log2n) != 0) return MW_EMODULUS;
+  mwhost::u128 r = mwhost::canonical_root(Q, 1u << log2n);
+  if (!r) return MW_EROOT;
+  mwhost::to_words(r, psi_out, limbs);
+  return MW_OK;
+}
+
+extern "C" int mw_shoup_companion(const uint64_t* w, const uint64_t* q, uint32_t limbs, uint64_t* out) {
+  if (!w || !q || !out || (limbs != 1 && limbs != 2)) return MW_EINVAL;
+  mwhost::u128 Q = mwhost::from_words(q, limbs), Wv = mwhost::from_words(w, limbs);
+  if (!width_ok(Q, limbs)) return MW_EMODULUS;
+  if (Wv >= Q) return MW_EINVAL;
+  mwhost::to_words(mwhost::shoup(Wv, Q, 64 * (int)limbs), out, limbs);
+  return MW_OK;
+}
+
+extern "C" int mw_barrett_mu(const uint64_t* q, uint32_t limbs, uint64_t* out) {
+  if (!q || !out || (limbs != 1 && limbs != 2)) return MW_EINVAL;
+  mwhost::u128 Q = mwhost::from_words(q, limbs);
+  if (!width_ok(Q, limbs)) return MW_EMODULUS;
+  mwhost::to_words(mwhost::pow2_div(2 * mwhost::bitlen(Q), Q), out, limbs);
+  return MW_OK;
+}

@@ -1,0 +1,249 @@
+"""Python binding of libmwntt.so (ctypes): argument marshalling only.
+
+Every function here forwards to the C ABI declared in include/mwntt.h; the
+arithmetic runs in the library's HIP kernels.  There is no CPU fallback: if the
+library is missing, importing the functions raises.
+
+Device buffers are torch tensors (any integer dtype, contiguous, on the GPU)
+holding `limbs` little-endian 64-bit words per residue, or raw device pointers
+(ints).  Moduli, roots and scalars are Python ints.  ``stream`` defaults to
+torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmwntt.so")
+
+MW_OK = 0
+NTT_BITREV_OUT = 0x1
+NTT_BITREV_IN = 0x2
+
+_lib = None
+
+
+class MwError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} ({status})")
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmwntt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2509_12494_amd.build` (or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64p, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t
+    sig = {
+        "mw_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+        "mw_version": (ctypes.c_char_p, []),
+        "vec_addmod": (ctypes.c_int, [vp, vp, vp, sz, u64p, u32, vp]),
+        "vec_submod": (ctypes.c_int, [vp, vp, vp, sz, u64p, u32, vp]),
+        "vec_mulmod": (ctypes.c_int, [vp, vp, vp, sz, u64p, u32, vp]),
+        "vec_axpymod": (ctypes.c_int, [vp, u64p, vp, sz, u64p, u32, vp]),
+        "ntt_plan": (ctypes.c_int, [ctypes.POINTER(vp), u32, u64p, u32, u64p, u32]),
+        "ntt_plan_destroy": (ctypes.c_int, [vp]),
+        "ntt_plan_root": (ctypes.c_int, [vp, u64p]),
+        "ntt_plan_set_split": (ctypes.c_int, [vp, u32]),
+        "ntt_plan_get_split": (ctypes.c_int, [vp, ctypes.POINTER(u32)]),
+        "ntt_forward": (ctypes.c_int, [vp, vp, vp, u32, vp]),
+        "ntt_inverse": (ctypes.c_int, [vp, vp, vp, u32, vp]),
+        "mw_canonical_root": (ctypes.c_int, [u64p, u32, u32, u64p]),
+        "mw_shoup_companion": (ctypes.c_int, [u64p, u64p, u32, u64p]),
+        "mw_barrett_mu": (ctypes.c_int, [u64p, u32, u64p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def status_str(status: int) -> str:
+    return lib().mw_status_str(status).decode()
+
+
+def version() -> str:
+    return lib().mw_version().decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != MW_OK:
+        raise MwError(status, where)
+
+
+def _words(x: int, limbs: int):
+    if x < 0 or x >= 1 << (64 * limbs):
+        raise ValueError("value does not fit the limb count")
+    arr = (ctypes.c_uint64 * 2)()
+    for i in range(limbs):
+        arr[i] = (x >> (64 * i)) & (2**64 - 1)
+    return arr
+
+
+def _from_words(arr, limbs: int) -> int:
+    return sum(int(arr[i]) << (64 * i) for i in range(limbs))
+
+
+def _ptr(t) -> int:
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _count(t, limbs: int, n: Optional[int]) -> int:
+    if n is not None:
+        return n
+    if isinstance(t, int):
+        raise ValueError("n is required with raw pointers")
+    return t.numel() * t.element_size() // (8 * limbs)
+
+
+# ---------------------------------------------------------------------------
+# BLAS
+# ---------------------------------------------------------------------------
+def _blas(name, c, a, b, q, limbs, n, stream):
+    n = _count(c, limbs, n)
+    st = getattr(lib(), name)(_ptr(c), _ptr(a), _ptr(b), n, _words(q, limbs), limbs, _stream(stream))
+    _check(st, name)
+
+
+def vec_addmod(c, a, b, q: int, limbs: int, n: Optional[int] = None, stream=None) -> None:
+    _blas("vec_addmod", c, a, b, q, limbs, n, stream)
+
+
+def vec_submod(c, a, b, q: int, limbs: int, n: Optional[int] = None, stream=None) -> None:
+    _blas("vec_submod", c, a, b, q, limbs, n, stream)
+
+
+def vec_mulmod(c, a, b, q: int, limbs: int, n: Optional[int] = None, stream=None) -> None:
+    _blas("vec_mulmod", c, a, b, q, limbs, n, stream)
+
+
+def vec_axpymod(y, alpha: int, x, q: int, limbs: int, n: Optional[int] = None, stream=None) -> None:
+    n = _count(y, limbs, n)
+    st = lib().vec_axpymod(_ptr(y), _words(alpha, limbs), _ptr(x), n, _words(q, limbs), limbs, _stream(stream))
+    _check(st, "vec_axpymod")
+
+
+# ---------------------------------------------------------------------------
+# NTT
+# ---------------------------------------------------------------------------
+class NttPlan:
+    """Owning wrapper of an ntt_plan_t."""
+
+    def __init__(self, log2n: int, q: int, limbs: int, psi: Optional[int] = None, flags: int = 0):
+        self.log2n, self.q, self.limbs, self.flags = log2n, q, limbs, flags
+        h = ctypes.c_void_p()
+        psi_w = _words(psi, limbs) if psi is not None else None
+        _check(lib().ntt_plan(ctypes.byref(h), log2n, _words(q, limbs), limbs, psi_w, flags), "ntt_plan")
+        self._h = h
+
+    @property
+    def n(self) -> int:
+        return 1 << self.log2n
+
+    @property
+    def root(self) -> int:
+        out = (ctypes.c_uint64 * 2)()
+        _check(lib().ntt_plan_root(self._h, out), "ntt_plan_root")
+        return _from_words(out, self.limbs)
+
+    @property
+    def split(self) -> int:
+        v = ctypes.c_uint32()
+        _check(lib().ntt_plan_get_split(self._h, ctypes.byref(v)), "ntt_plan_get_split")
+        return v.value
+
+    @split.setter
+    def split(self, log_n1: int) -> None:
+        _check(lib().ntt_plan_set_split(self._h, log_n1), "ntt_plan_set_split")
+
+    def _batch(self, t, batch):
+        if batch is not None:
+            return batch
+        if isinstance(t, int):
+            raise ValueError("batch is required with raw pointers")
+        return t.numel() * t.element_size() // (8 * self.limbs * self.n)
+
+    def forward(self, out, inp, batch: Optional[int] = None, stream=None) -> None:
+        b = self._batch(inp, batch)
+        _check(lib().ntt_forward(self._h, _ptr(out), _ptr(inp), b, _stream(stream)), "ntt_forward")
+
+    def inverse(self, out, inp, batch: Optional[int] = None, stream=None) -> None:
+        b = self._batch(inp, batch)
+        _check(lib().ntt_inverse(self._h, _ptr(out), _ptr(inp), b, _stream(stream)), "ntt_inverse")
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().ntt_plan_destroy(self._h), "ntt_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def ntt_plan(log2n: int, q: int, limbs: int, psi: Optional[int] = None, flags: int = 0) -> NttPlan:
+    return NttPlan(log2n, q, limbs, psi, flags)
+
+
+# ---------------------------------------------------------------------------
+# host-only helpers
+# ---------------------------------------------------------------------------
+def canonical_root(q: int, limbs: int, log2n: int) -> int:
+    out = (ctypes.c_uint64 * 2)()
+    _check(lib().mw_canonical_root(_words(q, limbs), limbs, log2n, out), "mw_canonical_root")
+    return _from_words(out, limbs)
+
+
+def shoup_companion(w: int, q: int, limbs: int) -> int:
+    out = (ctypes.c_uint64 * 2)()
+    _check(lib().mw_shoup_companion(_words(w, limbs), _words(q, limbs), limbs, out), "mw_shoup_companion")
+    return _from_words(out, limbs)
+
+
+def barrett_mu(q: int, limbs: int) -> int:
+    out = (ctypes.c_uint64 * 2)()
+    _check(lib().mw_barrett_mu(_words(q, limbs), limbs, out), "mw_barrett_mu")
+    return _from_words(out, limbs)
+
+
+# ---------------------------------------------------------------------------
+# tensor helpers (layout only)
+# ---------------------------------------------------------------------------
+def to_device(arr, device="cuda"):
+    """(n, limbs) uint64 numpy array -> int64 torch tensor on the device."""
+    import numpy as np
+    import torch
+    a = np.ascontiguousarray(arr, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def to_host(t):
+    """int64 torch tensor -> uint64 numpy array of the same shape."""
+    import numpy as np
+    return t.detach().cpu().numpy().view(np.uint64)

@@ -1,0 +1,123 @@
+"""Element-wise modular BLAS on the GPU against the oracle, bit for bit.
+
+Covers both widths (60-bit moduli in one limb, 124-bit in two), lengths that
+are multiples of the kernel's 1024-residue chunk and ragged ones, the paper
+scale length 2^16, every pair of edge residues, exact aliasing (c == a) and
+edge scalars for axpy."""
+import itertools
+
+import pytest
+
+import oracle
+from paper_2509_12494_amd import mwntt
+from paper_2509_12494_amd import workloads as W
+
+from .gpu_util import announce, dev, edge_values, host_ints, prime, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [(60, 11), (124, 12), (124, 2001), (97, 13), (33, 14)]
+SIZES = [1, 7, 1024, 1024 + 37, 3 * 4096 + 5, 1 << 16]
+OPS = ["vec_addmod", "vec_submod", "vec_mulmod"]
+
+
+def _oracle(op, a, b, q):
+    return getattr(oracle.modarith, op)(a, b, q)
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("op", OPS)
+def test_binary_ops(op, n, bits, seed):
+    require_gpu()
+    import torch
+    q = prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    g = W.rng(n * 7 + bits)
+    A = W.uniform_residues(g, q, n, limbs)
+    B = W.uniform_residues(g, q, n, limbs)
+    announce(op, n, bits)
+    a, b = dev(A), dev(B)
+    c = torch.empty_like(a)
+    getattr(mwntt, op)(c, a, b, q, limbs)
+    torch.cuda.synchronize()
+    assert host_ints(c, limbs) == _oracle(op, W.to_ints(A), W.to_ints(B), q)
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+@pytest.mark.parametrize("n", SIZES)
+def test_axpy(n, bits, seed):
+    require_gpu()
+    import torch
+    q = prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    g = W.rng(n * 11 + bits)
+    X = W.uniform_residues(g, q, n, limbs)
+    Y = W.uniform_residues(g, q, n, limbs)
+    alpha = W.uniform_scalar(g, q, limbs)
+    announce("axpy", n, bits)
+    x, y = dev(X), dev(Y)
+    mwntt.vec_axpymod(y, alpha, x, q, limbs)
+    torch.cuda.synchronize()
+    assert host_ints(y, limbs) == oracle.modarith.vec_axpymod(alpha, W.to_ints(X), W.to_ints(Y), q)
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+def test_edge_pairs(bits, seed):
+    require_gpu()
+    import torch
+    q = prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    ev = edge_values(q)
+    pairs = list(itertools.product(ev, ev))
+    a_i = [x for x, _ in pairs]
+    b_i = [y for _, y in pairs]
+    a, b = dev(W.from_ints(a_i, limbs)), dev(W.from_ints(b_i, limbs))
+    for op in OPS:
+        announce("edge", op, bits)
+        c = torch.empty_like(a)
+        getattr(mwntt, op)(c, a, b, q, limbs)
+        torch.cuda.synchronize()
+        assert host_ints(c, limbs) == _oracle(op, a_i, b_i, q), op
+    for alpha in ev:
+        announce("edge axpy", alpha, bits)
+        y = b.clone()
+        mwntt.vec_axpymod(y, alpha, a, q, limbs)
+        torch.cuda.synchronize()
+        assert host_ints(y, limbs) == oracle.modarith.vec_axpymod(alpha, a_i, b_i, q)
+
+
+@pytest.mark.parametrize("bits,seed", [(60, 11), (124, 12)])
+def test_in_place_aliasing(bits, seed):
+    require_gpu()
+    import torch
+    q = prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    n = 5000
+    g = W.rng(99)
+    A = W.uniform_residues(g, q, n, limbs)
+    B = W.uniform_residues(g, q, n, limbs)
+    for op in OPS:
+        announce("alias", op, bits)
+        a, b = dev(A), dev(B)
+        getattr(mwntt, op)(a, a, b, q, limbs)          # c == a
+        getattr(mwntt, op)(b, a, b, q, limbs)          # c == b
+        torch.cuda.synchronize()
+        first = _oracle(op, W.to_ints(A), W.to_ints(B), q)
+        assert host_ints(a, limbs) == first
+        assert host_ints(b, limbs) == _oracle(op, first, W.to_ints(B), q)
+
+
+def test_sub_range_of_buffer():
+    """n smaller than the buffer: residues past n are untouched."""
+    require_gpu()
+    import torch
+    q = prime(124, 12)
+    A = W.uniform_residues(W.rng(5), q, 3000, 2)
+    a = dev(A)
+    c = torch.zeros_like(a)
+    mwntt.vec_addmod(c, a, a, q, 2, n=2049)
+    torch.cuda.synchronize()
+    got = host_ints(c, 2)
+    assert got[:2049] == oracle.modarith.vec_addmod(W.to_ints(A)[:2049], W.to_ints(A)[:2049], q)
+    assert got[2049:] == [0] * (3000 - 2049)

@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+header declares, its host-side plan arithmetic matches the oracle, and argument
+errors are reported without touching the device."""
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_2509_12494_amd import mwntt
+from paper_2509_12494_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M):
+            if m.group(1) not in ("if", "while", "for", "return", "sizeof"):
+                names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = mwntt.lib()
+    names = declared_functions()
+    assert "ntt_forward" in names and "vec_axpymod" in names and len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings():
+    assert mwntt.status_str(0) == "ok"
+    assert "modulus" in mwntt.status_str(-2)
+    assert mwntt.version().startswith("mwntt")
+
+
+@pytest.mark.parametrize("bits,seed", [(60, 1), (60, 3001), (124, 1001), (124, 2001), (124, 4001)])
+def test_canonical_root_matches_oracle(bits, seed):
+    q = W.find_prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    for log2n in (1, 2, 5, 10, 13, 16, 17):
+        assert mwntt.canonical_root(q, limbs, log2n) == oracle.roots.canonical_psi(q, 1 << log2n)
+
+
+def test_canonical_root_small_primes():
+    # one-word moduli down to tiny primes (the Shoup/Barrett-free host path)
+    for q, n in ((17, 8), (97, 16), (7681, 256), (12289, 1024)):
+        log2n = n.bit_length() - 1
+        assert mwntt.canonical_root(q, 1, log2n) == oracle.roots.canonical_psi(q, n)
+
+
+@pytest.mark.parametrize("bits", [60, 124])
+def test_shoup_and_barrett_constants(bits):
+    q = W.find_prime(bits, 77)
+    limbs = W.limbs_for_bits(bits)
+    g = W.rng(3)
+    ws = W.to_ints(W.uniform_residues(g, q, 50, limbs)) + [0, 1, q - 1]
+    for w in ws:
+        assert mwntt.shoup_companion(w, q, limbs) == (w << (64 * limbs)) // q
+    assert mwntt.barrett_mu(q, limbs) == (1 << (2 * q.bit_length())) // q
+
+
+def test_argument_errors_without_device():
+    q60 = W.find_prime(60, 1)
+    q124 = W.find_prime(124, 1001)
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.ntt_plan(10, q60 + 1, 1)              # even modulus
+    assert e.value.status == -2
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.ntt_plan(18, q60, 1)                  # N above 2^17
+    assert e.value.status == -3
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.ntt_plan(0, q60, 1)
+    assert e.value.status == -3
+    with pytest.raises(ValueError):
+        mwntt.ntt_plan(10, q124, 1)                 # 124-bit q does not fit one limb
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.ntt_plan(10, q60, 2)                  # 60-bit q in two limbs
+    assert e.value.status == -2
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.ntt_plan(10, q60, 1, psi=2)           # not a primitive 2N-th root
+    assert e.value.status == -6
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.ntt_plan(10, q60, 1, flags=0x10)
+    assert e.value.status == -1
+    q_bad = (1 << 59) + 3                          # odd but not 1 mod 2N
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.ntt_plan(10, q_bad, 1)
+    assert e.value.status == -2
+    # BLAS: n == 0 is a no-op, null pointers and bad widths are rejected
+    mwntt.vec_addmod(0, 0, 0, q60, 1, n=0, stream=0)
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.vec_addmod(0, 0, 0, q60, 1, n=5, stream=0)
+    assert e.value.status == -1
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.vec_mulmod(8, 8, 8, (1 << 40) + 1 - 2**20, 2, n=5, stream=0)   # width mismatch
+    assert e.value.status == -2
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.vec_mulmod(8, 8, 8, 12289, 1, n=5, stream=0)  # Barrett needs >= 33 bits
+    assert e.value.status == -2
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.vec_axpymod(8, q60, 8, q60, 1, n=5, stream=0)  # alpha not reduced
+    assert e.value.status == -1

@@ -1,0 +1,253 @@
+"""Negacyclic NTT / INTT on the GPU against the oracle, bit for bit.
+
+* every single-workgroup size 2^1 .. 2^10, both widths, whole outputs against
+  the oracle's definition (O(N^2));
+* the two-pass path forced at small N over several splits (several column and
+  row tiles), whole outputs against the oracle;
+* the default configuration at 2^11 .. 2^17 (the paper-scale 2^16 included):
+  sampled outputs computed one by one from the definition, plus
+  INTT(NTT(a)) = a for the whole batch;
+* batches (including more polynomials than one scratch chunk), bit-reversed
+  I/O flags, a caller-supplied root, in-place transforms, edge inputs (zeros,
+  all q-1, impulses).
+"""
+import functools
+
+import pytest
+
+import oracle
+from paper_2509_12494_amd import mwntt
+from paper_2509_12494_amd import workloads as W
+
+from .gpu_util import announce, bitrev, dev, host_ints, prime, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [(60, 21), (124, 22)]
+
+
+@functools.lru_cache(maxsize=None)
+def _case(bits, seed, log2n, batch=1, kind="uniform"):
+    q = prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    n = 1 << log2n
+    if kind == "uniform":
+        A = W.uniform_residues(W.rng(1000 * log2n + batch), q, n * batch, limbs)
+    elif kind == "max":
+        A = W.from_ints([q - 1] * (n * batch), limbs)
+    elif kind == "zero":
+        A = W.from_ints([0] * (n * batch), limbs)
+    else:
+        raise ValueError(kind)
+    return q, limbs, A
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_fwd(bits, seed, log2n, batch=1, kind="uniform"):
+    q, limbs, A = _case(bits, seed, log2n, batch, kind)
+    n = 1 << log2n
+    a = W.to_ints(A)
+    return [oracle.ntt.ntt_negacyclic(a[i * n:(i + 1) * n], q) for i in range(batch)]
+
+
+def _run(plan, A, direction, batch=1, inplace=False):
+    import torch
+    x = dev(A)
+    y = x if inplace else torch.empty_like(x)
+    (plan.forward if direction == "fwd" else plan.inverse)(y, x, batch=batch)
+    torch.cuda.synchronize()
+    return y
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+@pytest.mark.parametrize("log2n", list(range(1, 11)))
+def test_single_tile_full(log2n, bits, seed):
+    require_gpu()
+    q, limbs, A = _case(bits, seed, log2n, 2)
+    n = 1 << log2n
+    want = _oracle_fwd(bits, seed, log2n, 2)
+    announce("single-tile fwd", log2n, bits)
+    plan = mwntt.ntt_plan(log2n, q, limbs)
+    assert plan.split == 0
+    y = _run(plan, A, "fwd", batch=2)
+    got = host_ints(y, limbs)
+    assert got[:n] == want[0] and got[n:] == want[1]
+    announce("single-tile inv", log2n, bits)
+    back = _run(plan, W.from_ints(want[0] + want[1], limbs), "inv", batch=2)
+    assert host_ints(back, limbs) == W.to_ints(A)
+    # the inverse against its own definition on an independent input
+    Bv = W.uniform_residues(W.rng(77 + log2n), q, n, limbs)
+    z = _run(plan, Bv, "inv")
+    assert host_ints(z, limbs) == oracle.ntt.intt_negacyclic(W.to_ints(Bv), q)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+@pytest.mark.parametrize("log2n,log_n1", [(6, 3), (8, 3), (8, 5), (10, 3), (10, 4), (10, 5), (10, 6), (10, 7),
+                                          (11, 3), (11, 5), (11, 8)])
+def test_two_pass_forced_full(log2n, log_n1, bits, seed):
+    require_gpu()
+    batch = 2
+    q, limbs, A = _case(bits, seed, log2n, batch)
+    n = 1 << log2n
+    want = _oracle_fwd(bits, seed, log2n, batch)
+    announce("two-pass fwd", log2n, log_n1, bits)
+    plan = mwntt.ntt_plan(log2n, q, limbs)
+    plan.split = log_n1
+    y = _run(plan, A, "fwd", batch=batch)
+    got = host_ints(y, limbs)
+    for i in range(batch):
+        assert got[i * n:(i + 1) * n] == want[i], f"poly {i}"
+    announce("two-pass inv", log2n, log_n1, bits)
+    back = _run(plan, W.from_ints(sum(want, []), limbs), "inv", batch=batch)
+    assert host_ints(back, limbs) == W.to_ints(A)
+    plan.destroy()
+
+
+SAMPLES = 24
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS + [(124, 2001)])
+@pytest.mark.parametrize("log2n", [11, 12, 13, 14, 15, 16, 17])
+def test_default_config_sampled(log2n, bits, seed):
+    require_gpu()
+    batch = 2
+    q, limbs, A = _case(bits, seed, log2n, batch)
+    n = 1 << log2n
+    announce("default fwd", log2n, bits)
+    plan = mwntt.ntt_plan(log2n, q, limbs)
+    y = _run(plan, A, "fwd", batch=batch)
+    got = host_ints(y, limbs)
+    a = W.to_ints(A)
+    g = W.rng(log2n)
+    ks = sorted(set([0, 1, n - 1, n // 2] + [int(k) for k in g.integers(0, n, SAMPLES)]))
+    for i in range(batch):
+        want = oracle.ntt.forward_at(a[i * n:(i + 1) * n], q, ks)
+        assert [got[i * n + k] for k in ks] == want, f"poly {i}"
+    announce("default inv", log2n, bits)
+    back = _run(plan, W.from_ints(got, limbs), "inv", batch=batch)
+    assert host_ints(back, limbs) == a
+    # inverse by definition at sampled indices, on the GPU's own forward output
+    js = ks[:8]
+    assert oracle.ntt.inverse_at(got[:n], q, js) == [a[j] for j in js]
+    plan.destroy()
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+def test_batch_beyond_scratch_chunk(bits, seed):
+    """2^17-point transforms, more polynomials than one 64 MiB scratch chunk."""
+    require_gpu()
+    import torch
+    log2n = 17
+    q = prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    n = 1 << log2n
+    per_chunk = (64 << 20) // (8 * limbs * n)
+    batch = per_chunk + 3
+    A = W.uniform_residues(W.rng(5), q, n * batch, limbs)
+    announce("chunked batch", batch, bits)
+    plan = mwntt.ntt_plan(log2n, q, limbs)
+    x = dev(A)
+    y = torch.empty_like(x)
+    plan.forward(y, x, batch=batch)
+    z = torch.empty_like(x)
+    plan.inverse(z, y, batch=batch)
+    torch.cuda.synchronize()
+    assert torch.equal(z, x)
+    got = host_ints(y[(batch - 1) * n:], limbs)     # last polynomial
+    a = W.to_ints(A[(batch - 1) * n:])
+    ks = [0, 3, n - 1]
+    assert [got[k] for k in ks] == oracle.ntt.forward_at(a, q, ks)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+@pytest.mark.parametrize("log2n,log_n1", [(9, 0), (10, 5), (14, 7)])
+def test_bitrev_flags(log2n, log_n1, bits, seed):
+    require_gpu()
+    q, limbs, A = _case(bits, seed, log2n)
+    n = 1 << log2n
+    announce("bitrev", log2n, log_n1, bits)
+    nat = mwntt.ntt_plan(log2n, q, limbs)
+    br = mwntt.ntt_plan(log2n, q, limbs, flags=mwntt.NTT_BITREV_OUT | mwntt.NTT_BITREV_IN)
+    if log_n1:
+        nat.split = log_n1
+        br.split = log_n1
+    yn = host_ints(_run(nat, A, "fwd"), limbs)
+    yb_t = _run(br, A, "fwd")
+    yb = host_ints(yb_t, limbs)
+    assert yb == [yn[bitrev(i, log2n)] for i in range(n)]
+    back = _run(br, mwntt.to_host(yb_t).reshape(-1, limbs), "inv")
+    assert host_ints(back, limbs) == W.to_ints(A)
+    nat.destroy()
+    br.destroy()
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+def test_custom_root_and_in_place(bits, seed):
+    require_gpu()
+    log2n = 8
+    q, limbs, A = _case(bits, seed, log2n)
+    psi = pow(oracle.roots.canonical_psi(q, 1 << log2n), 5, q)   # another primitive 2N-th root
+    announce("custom root", bits)
+    plan = mwntt.ntt_plan(log2n, q, limbs, psi=psi)
+    assert plan.root == psi
+    y = _run(plan, A, "fwd", inplace=True)
+    assert host_ints(y, limbs) == oracle.ntt.ntt_negacyclic(W.to_ints(A), q, psi=psi)
+    for log_n1 in (0, 4):
+        plan.split = log_n1
+        z = _run(plan, mwntt.to_host(y).reshape(-1, limbs), "inv", inplace=True)
+        assert host_ints(z, limbs) == W.to_ints(A)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+@pytest.mark.parametrize("log2n,log_n1", [(10, 0), (10, 5), (16, 8)])
+@pytest.mark.parametrize("kind", ["max", "zero"])
+def test_edge_inputs(kind, log2n, log_n1, bits, seed):
+    require_gpu()
+    q, limbs, A = _case(bits, seed, log2n, 1, kind)
+    n = 1 << log2n
+    announce("edge", kind, log2n, log_n1, bits)
+    plan = mwntt.ntt_plan(log2n, q, limbs)
+    if log_n1:
+        plan.split = log_n1
+    y = host_ints(_run(plan, A, "fwd"), limbs)
+    if kind == "zero":
+        assert y == [0] * n
+    else:
+        # a_j = -1 for all j: A_k = -sum_j psi^(j(2k+1)) = -(1 - psi^(N(2k+1)))/(1 - psi^(2k+1))
+        #                         = -2 / (1 - psi^(2k+1))  since psi^N = -1
+        psi = plan.root
+        ks = [0, 1, 2, n // 3, n - 1]
+        want = [(-2 * pow(1 - pow(psi, 2 * k + 1, q), -1, q)) % q for k in ks]
+        assert [y[k] for k in ks] == want
+    back = host_ints(_run(plan, W.from_ints(y, limbs), "inv"), limbs)
+    assert back == W.to_ints(A)
+    # inverse of all q-1 spectra
+    z = host_ints(_run(plan, A, "inv"), limbs)
+    if kind == "zero":
+        assert z == [0] * n
+    else:
+        js = [0, 1, n - 1]
+        assert [z[j] for j in js] == oracle.ntt.inverse_at(W.to_ints(A), q, js)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+def test_impulses(bits, seed):
+    require_gpu()
+    log2n = 12
+    q = prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    n = 1 << log2n
+    plan = mwntt.ntt_plan(log2n, q, limbs)
+    psi = plan.root
+    for j in (0, 1, n - 1):
+        announce("impulse", j, bits)
+        a = [0] * n
+        a[j] = 1
+        y = host_ints(_run(plan, W.from_ints(a, limbs), "fwd"), limbs)
+        ks = [0, 5, n - 1]
+        assert [y[k] for k in ks] == [pow(psi, j * (2 * k + 1), q) for k in ks]
+    plan.destroy()
