@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=96, help="transforms per call in the batched leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; runs on more than one GPU are not supported", file=sys.stderr)
@@ -201,6 +203,15 @@ def main():
                      "ops_per_butterfly": butterfly_word_ops(W_words)},
         "wall_s_timed_region": round(wall, 4),
     }
+    if args.copy_calibration_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
+        # the counters of the transform kernels to bytes
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda").fill_(3)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = nbytes
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl)
     plan.destroy()

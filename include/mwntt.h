@@ -116,6 +116,16 @@ int ntt_plan_root(ntt_plan_t plan, uint64_t* psi_out);
 int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1);
 int ntt_plan_get_split(ntt_plan_t plan, uint32_t* log_n1);
 
+/* Tile shape of one pass (pass 0: single-workgroup transform, 1: column pass,
+ * 2: row pass): 2^log_p points per lane (1 <= log_p <= 4) and `lines`
+ * sub-transforms per workgroup (a power of two; columns per column tile, rows
+ * per row tile, transforms per single-workgroup tile).  Rejected (MW_EINVAL)
+ * when the pass is not part of the plan's current split or the workgroup would
+ * exceed its thread or LDS limits.  ntt_plan_set_split resets the shapes to
+ * their defaults.  Results do not depend on the shape. */
+int ntt_plan_set_tiles(ntt_plan_t plan, uint32_t pass, uint32_t log_p, uint32_t lines);
+int ntt_plan_get_tiles(ntt_plan_t plan, uint32_t pass, uint32_t* log_p, uint32_t* lines);
+
 /* Transforms `batch` polynomials [batch][N][limbs].  d_out == d_in is
  * allowed.  Calls on one plan must not overlap in time on different streams
  * (they share the plan's scratch buffer); plans are independent. */

@@ -18,7 +18,12 @@ LIB = os.path.join(HERE, "libmwntt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["mw_blas.hip", "mw_ntt.hip", "mw_capi.cpp"]
+SOURCES = ["mw_ntt_w4_fwd.hip", "mw_ntt_w4_inv.hip", "mw_ntt_w2_fwd.hip", "mw_ntt_w2_inv.hip",
+           "mw_blas.hip", "mw_ntt.hip", "mw_capi.cpp"]
+# Sources whose kernels are scheduled for instruction-level parallelism: the
+# multi-word carry chains otherwise serialize on VCC with hazard wait states.
+ILP_SOURCES = {"mw_ntt_w4_fwd.hip", "mw_ntt_w4_inv.hip", "mw_ntt_w2_fwd.hip", "mw_ntt_w2_inv.hip"}
+ILP_FLAGS = ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-DMWNTT_MIN_WAVES_PER_EU=3"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]
 # device-code flags: every HIP source goes through hipcc for gfx950
@@ -27,7 +32,8 @@ HIP_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", 
 
 def _compile(src, verbose):
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ILP_FLAGS if src in ILP_SOURCES else []
+    cmd = [HIPCC] + COMMON + HIP_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

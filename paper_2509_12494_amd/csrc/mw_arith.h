@@ -51,6 +51,7 @@ struct Modulus {
   u32 q4[W];   // 4q
   u32 q8[W];   // 8q
   u32 mu[W];   // Barrett mu = floor(2^(2b)/q) (b+1 bits)
+  u32 negq[W]; // 2^(32W) - q
   u32 bits;    // b = bitlen(q)
   u32 pad_[3];
 };
@@ -188,6 +189,53 @@ __device__ __forceinline__ Res<2> mul_lo(const Res<2>& a, const u32 (&b)[2]) {
   return r;
 }
 
+// low W words of x*w + Q*nq: the Shoup remainder x*w - Q*q modulo 2^(32W)
+// when nq = 2^(32W) - q, as one accumulation.
+__device__ __forceinline__ Res<4> mul_lo2(const Res<4>& x, const u32 (&w)[4], const Res<4>& Q, const u32 (&nq)[4]) {
+  Res<4> r;
+  // column 0
+  u64 acc = (u64)x.v[0] * w[0];
+  u64 cc = mad_cc(Q.v[0], nq[0], acc);
+  u32 t = add_carry(0u, cc);
+  r.v[0] = lo32(acc);
+  // column 1: carry-in {hi, t} < 2^33 so the first product cannot overflow
+  acc = pack(hi32(acc), t);
+  acc = mad(x.v[0], w[1], acc);
+  cc = mad_cc(x.v[1], w[0], acc);
+  t = add_carry(0u, cc);
+  cc = mad_cc(Q.v[0], nq[1], acc);
+  t = add_carry(t, cc);
+  cc = mad_cc(Q.v[1], nq[0], acc);
+  t = add_carry(t, cc);
+  r.v[1] = lo32(acc);
+  // column 2 modulo 2^64 (only its low 64 bits reach words 2 and 3)
+  acc = pack(hi32(acc), t);
+  acc = mad(x.v[0], w[2], acc);
+  acc = mad(x.v[1], w[1], acc);
+  acc = mad(x.v[2], w[0], acc);
+  acc = mad(Q.v[0], nq[2], acc);
+  acc = mad(Q.v[1], nq[1], acc);
+  acc = mad(Q.v[2], nq[0], acc);
+  r.v[2] = lo32(acc);
+  // column 3: low word only
+  u32 c3 = hi32(acc);
+  c3 += x.v[0] * w[3] + x.v[1] * w[2] + x.v[2] * w[1] + x.v[3] * w[0];
+  c3 += Q.v[0] * nq[3] + Q.v[1] * nq[2] + Q.v[2] * nq[1] + Q.v[3] * nq[0];
+  r.v[3] = c3;
+  return r;
+}
+
+__device__ __forceinline__ Res<2> mul_lo2(const Res<2>& x, const u32 (&w)[2], const Res<2>& Q, const u32 (&nq)[2]) {
+  Res<2> r;
+  u64 acc = (u64)x.v[0] * w[0];
+  acc = mad(Q.v[0], nq[0], acc);        // column 0 modulo 2^64: only its high word is used below
+  r.v[0] = lo32(acc);
+  u32 c1 = hi32(acc);
+  c1 += x.v[0] * w[1] + x.v[1] * w[0] + Q.v[0] * nq[1] + Q.v[1] * nq[0];
+  r.v[1] = c1;
+  return r;
+}
+
 // Shoup quotient estimate: floor(sum over columns >= W-1 of x*ws / 2^(32W)).
 // Under-estimates floor(x*ws / 2^(32W)) by at most 4 (W=4) / 1 (W=2).
 __device__ __forceinline__ Res<4> mul_hi_est(const Res<4>& x, const u32 (&ws)[4]) {
@@ -313,10 +361,7 @@ template <int W>
 __device__ __forceinline__ Res<W> shoup_mul(const Res<W>& x, const u32 (&w)[W], const u32 (&ws)[W],
                                             const Modulus<W>& M) {
   Res<W> Q = mul_hi_est(x, ws);
-  Res<W> xw = mul_lo(x, w);
-  Res<W> qq = mul_lo(Q, M.q);
-  u32 b;
-  return sub(xw, qq, b);
+  return mul_lo2(x, w, Q, M.negq);
 }
 
 // funnel shift: bits [s, s+32) of the 64-bit value hi:lo, 0 <= s < 32

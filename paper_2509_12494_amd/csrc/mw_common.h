@@ -41,6 +41,7 @@ inline void make_modulus(const uint64_t* q, uint32_t limbs, Modulus<W>& M) {
   put_words<W>(4 * Q, M.q4);
   put_words<W>(8 * Q, M.q8);
   put_words<W>(mwhost::pow2_div(2 * b, Q), M.mu);
+  put_words<W>((mwhost::u128)0 - Q, M.negq);  // 2^(32W) - q (W = 4: 2^128 - q)
   M.bits = (u32)b;
   M.pad_[0] = M.pad_[1] = M.pad_[2] = 0;
 }

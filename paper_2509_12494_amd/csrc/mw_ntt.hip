@@ -1,415 +1,24 @@
-// Negacyclic NTT / INTT over Z_q[X]/(X^N + 1) for gfx950.
+// Negacyclic NTT plans and entry points (host side).
 //
-// What is computed (Background, polynomial multiplication using NTT, Eq. ntt):
-//   forward  A_k = sum_j a_j psi^(j(2k+1))             (Eq. ntt on a_j psi^j,
-//   inverse  a_j = N^-1 psi^-j sum_k A_k psi^(-2jk)      omega_N = psi^2)
-// An N-point transform is log N stages of N/2 butterflies, each one modular
-// multiplication, one addition and one subtraction (SIMD-vectorized kernels,
-// from arithmetic to cryptographic kernels).
-//
-// Algorithm.  The forward transform is the merged-psi Cooley-Tukey form:
-// stage s (m = 2^s groups, half-width t = N/2m) pairs j and j+t and
-// multiplies by tw[m + floor(j/2t)], tw[i] = psi^bitrev(i), leaving the output
-// in bit-reversed order.  The inverse is the Gentleman-Sande form with
-// tw'[i] = psi^-bitrev(i), processing the stages in reverse and taking
-// bit-reversed input; N^-1 is folded into its last stage.  Butterflies are
-// lazy (Harvey): forward values stay in [0, 16q), inverse values in [0, 8q),
-// with one conditional subtraction per butterfly; results are made canonical
-// once at the end.
-//
-// Data movement (the paper permutes between stages with AVX-512 unpack /
-// permute instructions; here stages exchange data through LDS):
-//   * a "line" is an n = 2^LOGL point sub-transform held by n/P lanes, each lane
-//     owning P = 2^LOGP points; LOGP stages run in registers per round, and
-//     lanes exchange points through LDS between rounds;
-//   * N <= 2^12 (2^13 for one-word moduli): one line per transform, the whole
-//     transform in one workgroup ("full" tiles);
-//   * larger N: N = N1 * N2 and two passes over HBM.  The first log N1
-//     Cooley-Tukey stages only pair elements in the same residue class mod N2
-//     (columns of stride N2) and use the table entries below N1, so a column
-//     is an N1-point line with twiddle base 1.  The remaining log N2 stages act
-//     within contiguous rows of N2 elements; row b is an N2-point line whose
-//     local stage m' uses tw[m' * (N1 + b) + g].  No transpose and no extra
-//     twiddle pass are needed.  The inverse runs the rows first, then the
-//     columns.
-//   * natural-order output of the forward transform: row b, local index l
-//     holds A at k = bitrev(l)*N1 + bitrev(b).  A row tile takes G rows
-//     b = j*(N1/G) + b_lo, whose outputs land in runs of G consecutive
-//     residues, so the permuted store (and the inverse's permuted load) is
-//     coalesced in G*16-byte segments.
+// A plan holds, per (q, N): the forward table tw[i] = psi^bitrev(i) and the
+// inverse table tw'[i] = psi^-bitrev(i), each entry with its Shoup companion
+// floor(w * 2^(32W) / q), in device memory; N^-1 constants for the last
+// inverse stage; the decomposition (single workgroup or N1 x N2 two-pass) and
+// the tile shape of each pass; and a scratch buffer for the two-pass
+// intermediate.  The transforms themselves are the tile kernels of
+// mw_ntt_tile.h (see the algorithm notes there).
 #include <hip/hip_runtime.h>
 
-#include <mutex>
 #include <new>
 #include <vector>
 
 #include "mw_arith.h"
 #include "mw_common.h"
+#include "mw_ntt_tile.h"
 
 namespace mw {
-
-template <int W>
-struct Tw {
-  u32 w[W];
-  u32 ws[W];
-};
-
-template <int W>
-__device__ __forceinline__ Tw<W> load_tw(const Tw<W>* t, u32 idx) {
-  Tw<W> r;
-  if constexpr (W == 4) {
-    const uint4* p = reinterpret_cast<const uint4*>(t + idx);
-    uint4 a = p[0], b = p[1];
-    r.w[0] = a.x; r.w[1] = a.y; r.w[2] = a.z; r.w[3] = a.w;
-    r.ws[0] = b.x; r.ws[1] = b.y; r.ws[2] = b.z; r.ws[3] = b.w;
-  } else {
-    uint4 a = *reinterpret_cast<const uint4*>(t + idx);
-    r.w[0] = a.x; r.w[1] = a.y;
-    r.ws[0] = a.z; r.ws[1] = a.w;
-  }
-  return r;
-}
-
-enum { DIR_FWD = 0, DIR_INV = 1 };
-enum { MODE_FULL = 0, MODE_COL = 1, MODE_ROW = 2 };
-
-template <int W>
-struct NttParams {
-  const Res<W>* src;     // input of this pass
-  Res<W>* dst;           // output of this pass
-  const Tw<W>* tw;       // this direction's table, N entries
-  Modulus<W> M;
-  Tw<W> ninv;            // N^-1 and its Shoup companion (inverse only)
-  Tw<W> ninv_w1;         // tw'[1] * N^-1 (inverse only)
-  u32 log_n;             // transform size
-  u32 log_n1;            // rows of the two-pass split (N1 = 2^log_n1)
-  u32 batch;
-  u32 permute;           // 1: natural order at the HBM side of this pass
-};
-
-// Forward (Cooley-Tukey) butterfly on [0, 16q) values.
-template <int W>
-__device__ __forceinline__ void ct_bfly(Res<W>& X, Res<W>& Y, const Tw<W>& t, const Modulus<W>& M) {
-  Res<W> T = shoup_mul(Y, t.w, t.ws, M);   // [0, 6q)
-  Res<W> Xr = csub(X, M.q8);               // [0, 8q)
-  X = add(Xr, T);                          // [0, 14q)
-  Res<W> D = add(Xr, M.q8);                // [8q, 16q)
-  u32 b;
-  Y = sub(D, T, b);                        // (2q, 16q)
-}
-
-// Inverse (Gentleman-Sande) butterfly on [0, 8q) values.
-template <int W>
-__device__ __forceinline__ void gs_bfly(Res<W>& X, Res<W>& Y, const Tw<W>& t, const Modulus<W>& M) {
-  Res<W> S = csub(add(X, Y), M.q8);        // [0, 8q)
-  Res<W> D = add(X, M.q8);
-  u32 b;
-  D = sub(D, Y, b);                        // (0, 16q)
-  Y = shoup_mul(D, t.w, t.ws, M);          // [0, 6q)
-  X = S;
-}
-
-// Last inverse stage with N^-1 folded in; outputs canonical.
-template <int W>
-__device__ __forceinline__ void gs_bfly_last(Res<W>& X, Res<W>& Y, const Tw<W>& ninv, const Tw<W>& ninv_w1,
-                                             const Modulus<W>& M) {
-  Res<W> S = add(X, Y);                    // [0, 16q) < 2^(32W)
-  Res<W> D = add(X, M.q8);
-  u32 b;
-  D = sub(D, Y, b);                        // (0, 16q)
-  Res<W> x = shoup_mul(S, ninv.w, ninv.ws, M);     // [0, 6q)
-  Res<W> y = shoup_mul(D, ninv_w1.w, ninv_w1.ws, M);
-  x = csub(csub(csub(x, M.q4), M.q2), M.q);
-  y = csub(csub(csub(y, M.q4), M.q2), M.q);
-  X = x;
-  Y = y;
-}
-
-template <int W>
-__device__ __forceinline__ Res<W> canon16(const Res<W>& x, const Modulus<W>& M) {
-  return csub(csub(csub(csub(x, M.q8), M.q4), M.q2), M.q);
-}
-
-__device__ __forceinline__ u32 brev(u32 x, u32 bits) {
-  return bits ? (__builtin_bitreverse32(x) >> (32 - bits)) : 0u;
-}
-
-// LDS slot of point j within a line: one padding slot after every P points.
-template <int LOGL, int LOGP>
-__device__ __forceinline__ u32 pad_idx(u32 j) {
-  if constexpr (LOGL > LOGP) return j + (j >> LOGP);
-  else return j;
-}
-
-template <int LOGL, int LOGP>
-struct LineShape {
-  static constexpr int L = 1 << LOGL;
-  static constexpr int P = 1 << LOGP;
-  static constexpr int TPL = L / P;                      // lanes per line
-  static constexpr int NPAD = (LOGL > LOGP) ? L + L / P : L;
-  static constexpr int R = (LOGL + LOGP - 1) / LOGP;     // rounds
-  static constexpr int P0 = LOGL - LOGP * (R - 1);       // stages in round 0
-};
-
-// One round of a line: LOGP (or, for round 0, the remainder P0) stages on the
-// P points a lane holds, between an LDS load and an LDS store.  In round r the
-// lane's point u sits at line index base_j | (u << L0), L0 = LOGL - s0 - LOGP;
-// the stages of the round pair the top np bits of u.  Rounds and stages are
-// compile-time recursions so every register index is a constant.
-template <int W, int LOGL, int LOGP, int DIR, int RIDX>
-struct Round {
-  using S = LineShape<LOGL, LOGP>;
-  static constexpr int P = S::P;
-  static constexpr int s0 = (RIDX == 0) ? 0 : S::P0 + (RIDX - 1) * LOGP;
-  static constexpr int np = (RIDX == 0) ? S::P0 : LOGP;
-  static constexpr int L0 = LOGL - s0 - LOGP;
-
-  template <int ST0>
-  static __device__ __forceinline__ void stage(Res<W> (&x)[P], u32 base_j, u32 base, const Tw<W>* __restrict__ tw,
-                                               const NttParams<W>& p, bool last_inv) {
-    constexpr int st = (DIR == DIR_FWD) ? ST0 : (np - 1 - ST0);
-    constexpr int s = s0 + st;              // stage index within the line
-    constexpr int ib = LOGP - 1 - st;       // bit of u that the stage pairs
-    constexpr int ngroups = 1 << st;        // distinct twiddles of the stage
-#pragma unroll
-    for (int gi = 0; gi < ngroups; ++gi) {
-      const u32 j0 = base_j | ((u32)(gi << (ib + 1)) << L0);
-      const u32 g = j0 >> (LOGL - s);
-      if (DIR == DIR_INV && s == 0 && last_inv) {
-#pragma unroll
-        for (int lo = 0; lo < (1 << ib); ++lo) {
-          const int u = (gi << (ib + 1)) | lo;
-          gs_bfly_last(x[u], x[u | (1 << ib)], p.ninv, p.ninv_w1, p.M);
-        }
-      } else {
-        const Tw<W> t = load_tw(tw, (base << s) + g);
-#pragma unroll
-        for (int lo = 0; lo < (1 << ib); ++lo) {
-          const int u = (gi << (ib + 1)) | lo;
-          if (DIR == DIR_FWD) ct_bfly(x[u], x[u | (1 << ib)], t, p.M);
-          else gs_bfly(x[u], x[u | (1 << ib)], t, p.M);
-        }
-      }
-    }
-    if constexpr (ST0 + 1 < np) stage<ST0 + 1>(x, base_j, base, tw, p, last_inv);
-  }
-
-  static __device__ __forceinline__ void run(Res<W>* line, u32 tid, u32 base, const Tw<W>* __restrict__ tw,
-                                             const NttParams<W>& p, bool last_inv, bool canon) {
-    const u32 base_j = ((tid >> L0) << (L0 + LOGP)) | (tid & ((1u << L0) - 1u));
-    Res<W> x[P];
-#pragma unroll
-    for (int u = 0; u < P; ++u) x[u] = line[pad_idx<LOGL, LOGP>(base_j | ((u32)u << L0))];
-    stage<0>(x, base_j, base, tw, p, last_inv);
-    if (canon) {
-#pragma unroll
-      for (int u = 0; u < P; ++u) x[u] = canon16(x[u], p.M);
-    }
-#pragma unroll
-    for (int u = 0; u < P; ++u) line[pad_idx<LOGL, LOGP>(base_j | ((u32)u << L0))] = x[u];
-    __syncthreads();
-  }
-};
-
-// All rounds of a line held in LDS (forward: rounds 0..R-1; inverse: R-1..0).
-// tid: lane index within the line; base: twiddle base (1, or N1 + b for rows);
-// last_inv: the line contains the final inverse stage (fold N^-1);
-// final_fwd: canonicalize after the last forward stage.
-template <int W, int LOGL, int LOGP, int DIR, int RR = 0>
-__device__ __forceinline__ void line_stages(Res<W>* line, u32 tid, u32 base, const Tw<W>* __restrict__ tw,
-                                            const NttParams<W>& p, bool last_inv, bool final_fwd) {
-  using S = LineShape<LOGL, LOGP>;
-  constexpr int R = (DIR == DIR_FWD) ? RR : (S::R - 1 - RR);
-  Round<W, LOGL, LOGP, DIR, R>::run(line, tid, base, tw, p, last_inv,
-                                    DIR == DIR_FWD && final_fwd && RR == S::R - 1);
-  if constexpr (RR + 1 < S::R) line_stages<W, LOGL, LOGP, DIR, RR + 1>(line, tid, base, tw, p, last_inv, final_fwd);
-}
-
-template <int W, int LOGL, int LOGP, int LINES, int DIR, int MODE>
-__global__ __launch_bounds__(LINES*(1 << (LOGL - LOGP))) void ntt_kernel(NttParams<W> p) {
-  using S = LineShape<LOGL, LOGP>;
-  constexpr int T = LINES * S::TPL;
-  constexpr int L = S::L;
-  __shared__ Res<W> lds[LINES * S::NPAD];
-
-  const u32 t = threadIdx.x;
-  const u32 line_id = t / S::TPL;
-  const u32 lane = t % S::TPL;
-  const u32 log_n = p.log_n;
-  const u64 N = (u64)1 << log_n;
-
-  u32 poly;
-  u32 c0 = 0, b_lo = 0, log_g = 0, log_n1 = p.log_n1, log_n2 = log_n - p.log_n1;
-  if (MODE == MODE_FULL) {
-    poly = blockIdx.x;   // LINES polys per block
-  } else if (MODE == MODE_COL) {
-    const u32 tiles = (1u << log_n2) / LINES;
-    poly = blockIdx.x / tiles;
-    c0 = (blockIdx.x % tiles) * LINES;
-  } else {
-    const u32 tiles = (1u << log_n1) / LINES;
-    poly = blockIdx.x / tiles;
-    b_lo = blockIdx.x % tiles;
-    log_g = __builtin_ctz((u32)LINES);
-  }
-
-  // ---- HBM -> LDS ----
-  if (MODE == MODE_FULL) {
-#pragma unroll
-    for (int k = 0; k < LINES * L / T; ++k) {
-      const u32 e = t + k * T;
-      const u32 ln = e >> LOGL, j = e & (L - 1);
-      const u64 pl = (u64)poly * LINES + ln;
-      if (pl < p.batch) {
-        const u32 dj = (DIR == DIR_INV && p.permute) ? brev(j, LOGL) : j;
-        lds[ln * S::NPAD + pad_idx<LOGL, LOGP>(dj)] = ResIO<W>::load(p.src + pl * N + j);
-      }
-    }
-  } else if (MODE == MODE_COL) {
-    const u64 N2 = (u64)1 << log_n2;
-#pragma unroll
-    for (int k = 0; k < LINES * L / T; ++k) {
-      const u32 e = t + k * T;
-      const u32 r = e / LINES, c = e % LINES;
-      lds[c * S::NPAD + pad_idx<LOGL, LOGP>(r)] = ResIO<W>::load(p.src + (u64)poly * N + r * N2 + c0 + c);
-    }
-  } else {
-    const u32 n1_over_g = (1u << log_n1) >> log_g;
-    if (DIR == DIR_INV && p.permute) {
-      // natural-order input: run of G residues at k = l'*N1 + bitrev(b_lo)*G + jj
-      const u32 col = brev(b_lo, log_n1 - log_g) << log_g;
-#pragma unroll
-      for (int k = 0; k < LINES * L / T; ++k) {
-        const u32 e = t + k * T;
-        const u32 lp = e / LINES, jj = e % LINES;
-        const u64 src = (u64)poly * N + ((u64)lp << log_n1) + col + jj;
-        lds[brev(jj, log_g) * S::NPAD + pad_idx<LOGL, LOGP>(brev(lp, LOGL))] = ResIO<W>::load(p.src + src);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < LINES * L / T; ++k) {
-        const u32 e = t + k * T;
-        const u32 j = e >> LOGL, l = e & (L - 1);
-        const u32 b = j * n1_over_g + b_lo;
-        lds[j * S::NPAD + pad_idx<LOGL, LOGP>(l)] = ResIO<W>::load(p.src + (u64)poly * N + ((u64)b << LOGL) + l);
-      }
-    }
-  }
-  __syncthreads();
-
-  // ---- stages ----
-  u32 base = 1;
-  if (MODE == MODE_ROW) base = (1u << log_n1) + line_id * ((1u << log_n1) >> log_g) + b_lo;
-  const bool last_inv = (DIR == DIR_INV) && (MODE != MODE_ROW);
-  const bool final_fwd = (DIR == DIR_FWD) && (MODE != MODE_COL);
-  line_stages<W, LOGL, LOGP, DIR>(lds + line_id * S::NPAD, lane, base, p.tw, p, last_inv, final_fwd);
-
-  // ---- LDS -> HBM ----
-  if (MODE == MODE_FULL) {
-#pragma unroll
-    for (int k = 0; k < LINES * L / T; ++k) {
-      const u32 e = t + k * T;
-      const u32 ln = e >> LOGL, j = e & (L - 1);
-      const u64 pl = (u64)poly * LINES + ln;
-      if (pl < p.batch) {
-        const u32 sj = (DIR == DIR_FWD && p.permute) ? brev(j, LOGL) : j;
-        ResIO<W>::store(p.dst + pl * N + j, lds[ln * S::NPAD + pad_idx<LOGL, LOGP>(sj)]);
-      }
-    }
-  } else if (MODE == MODE_COL) {
-    const u64 N2 = (u64)1 << log_n2;
-#pragma unroll
-    for (int k = 0; k < LINES * L / T; ++k) {
-      const u32 e = t + k * T;
-      const u32 r = e / LINES, c = e % LINES;
-      ResIO<W>::store(p.dst + (u64)poly * N + r * N2 + c0 + c, lds[c * S::NPAD + pad_idx<LOGL, LOGP>(r)]);
-    }
-  } else {
-    const u32 n1_over_g = (1u << log_n1) >> log_g;
-    if (DIR == DIR_FWD && p.permute) {
-      const u32 col = brev(b_lo, log_n1 - log_g) << log_g;
-#pragma unroll
-      for (int k = 0; k < LINES * L / T; ++k) {
-        const u32 e = t + k * T;
-        const u32 lp = e / LINES, jj = e % LINES;
-        const u64 dst = (u64)poly * N + ((u64)lp << log_n1) + col + jj;
-        ResIO<W>::store(p.dst + dst, lds[brev(jj, log_g) * S::NPAD + pad_idx<LOGL, LOGP>(brev(lp, LOGL))]);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < LINES * L / T; ++k) {
-        const u32 e = t + k * T;
-        const u32 j = e >> LOGL, l = e & (L - 1);
-        const u32 b = j * n1_over_g + b_lo;
-        ResIO<W>::store(p.dst + (u64)poly * N + ((u64)b << LOGL) + l, lds[j * S::NPAD + pad_idx<LOGL, LOGP>(l)]);
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// launch configuration
-// ---------------------------------------------------------------------------
-constexpr int kLogP = 3;           // 8 points per lane
-constexpr int kColLines = 8;       // columns per column tile
-constexpr int kRowLines = 8;       // rows per row tile
 constexpr int kMaxFullLog4 = 12;   // largest single-workgroup transform, two-word moduli
 constexpr int kMaxFullLog2 = 13;   // one-word moduli
-
-template <int LOGL>
-constexpr int full_lines() {
-  // aim at 256 lanes per block, at least one line
-  constexpr int lp = LOGL < kLogP ? LOGL : kLogP;
-  constexpr int tpl = 1 << (LOGL - lp);
-  return tpl >= 256 ? 1 : 256 / tpl;
-}
-
-template <int W, int LOGL, int DIR, int MODE>
-static hipError_t launch_one(const NttParams<W>& p, u32 blocks, hipStream_t s) {
-  constexpr int LOGP = LOGL < kLogP ? LOGL : kLogP;
-  constexpr int LINES = (MODE == MODE_FULL) ? full_lines<LOGL>() : (MODE == MODE_COL ? kColLines : kRowLines);
-  constexpr int T = LINES * (1 << (LOGL - LOGP));
-  hipLaunchKernelGGL((ntt_kernel<W, LOGL, LOGP, LINES, DIR, MODE>), dim3(blocks), dim3(T), 0, s, p);
-  return hipGetLastError();
-}
-
-// Line lengths instantiated per mode: single-workgroup transforms of 2^1 up to
-// 2^12 points (2^13 for one-word moduli); column / row lines of 2^3 .. 2^9.
-template <int W, int MODE>
-constexpr bool instantiated(int logl) {
-  if (MODE == MODE_FULL) return logl >= 1 && logl <= (W == 4 ? kMaxFullLog4 : kMaxFullLog2);
-  return logl >= 3 && logl <= 9;
-}
-
-template <int W, int DIR, int MODE>
-static hipError_t launch_by_log(u32 logl, const NttParams<W>& p, u32 blocks, hipStream_t s) {
-  switch (logl) {
-#define MW_CASE(LG)                                                                   \
-  case LG:                                                                            \
-    if constexpr (instantiated<W, MODE>(LG)) return launch_one<W, LG, DIR, MODE>(p, blocks, s); \
-    return hipErrorInvalidValue;
-    MW_CASE(1) MW_CASE(2) MW_CASE(3) MW_CASE(4) MW_CASE(5) MW_CASE(6) MW_CASE(7) MW_CASE(8) MW_CASE(9)
-    MW_CASE(10) MW_CASE(11) MW_CASE(12) MW_CASE(13)
-#undef MW_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
-}
-
-template <int W>
-static u32 full_lines_for(u32 logl) {
-  switch (logl) {
-#define MW_CASE(LG) \
-  case LG:          \
-    return full_lines<LG>();
-    MW_CASE(1) MW_CASE(2) MW_CASE(3) MW_CASE(4) MW_CASE(5) MW_CASE(6) MW_CASE(7) MW_CASE(8) MW_CASE(9)
-    MW_CASE(10) MW_CASE(11) MW_CASE(12) MW_CASE(13)
-#undef MW_CASE
-    default:
-      return 1;
-  }
-}
-
 }  // namespace mw
 
 // ---------------------------------------------------------------------------
@@ -417,9 +26,15 @@ static u32 full_lines_for(u32 logl) {
 // ---------------------------------------------------------------------------
 using namespace mw;
 
+struct PassCfg {
+  uint32_t logp = 3;          // points per lane, log2
+  uint32_t lines = 8;         // lines per tile
+};
+
 struct ntt_plan_s {
   uint32_t log2n = 0, limbs = 0, flags = 0;
   uint32_t log_n1 = 0;        // 0: single-tile transform
+  PassCfg cfg[3];             // MODE_FULL, MODE_COL, MODE_ROW
   uint64_t q[2] = {0, 0};
   uint64_t psi[2] = {0, 0};
   int device = 0;
@@ -492,6 +107,14 @@ void free_plan(ntt_plan_s* P) {
 constexpr size_t kScratchBytes = size_t(64) << 20;
 
 template <int W>
+hipError_t launch_pass(int dir, int mode, const ntt_plan_s* P, NttParams<W>& p, u32 blocks, hipStream_t s) {
+  const u32 logl = mode == MODE_FULL ? P->log2n : (mode == MODE_COL ? P->log_n1 : P->log2n - P->log_n1);
+  p.lines = P->cfg[mode].lines;
+  return dir == DIR_FWD ? launch_ntt<W, DIR_FWD>(mode, logl, P->cfg[mode].logp, p, blocks, s)
+                        : launch_ntt<W, DIR_INV>(mode, logl, P->cfg[mode].logp, p, blocks, s);
+}
+
+template <int W>
 int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, int dir, hipStream_t s) {
   NttParams<W> p = {};
   p.tw = reinterpret_cast<const Tw<W>*>(dir == DIR_FWD ? P->d_tw_fwd : P->d_tw_inv);
@@ -513,15 +136,12 @@ int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, 
     p.dst = reinterpret_cast<Res<W>*>(d_out);
     p.batch = batch;
     p.permute = dir == DIR_FWD ? !(P->flags & NTT_BITREV_OUT) : !(P->flags & NTT_BITREV_IN);
-    const u32 lines = full_lines_for<W>(P->log2n);
-    const u32 blocks = (batch + lines - 1) / lines;
-    e = dir == DIR_FWD ? launch_by_log<W, DIR_FWD, MODE_FULL>(P->log2n, p, blocks, s)
-                       : launch_by_log<W, DIR_INV, MODE_FULL>(P->log2n, p, blocks, s);
+    const u32 lines = P->cfg[MODE_FULL].lines;
+    e = launch_pass<W>(dir, MODE_FULL, P, p, (batch + lines - 1) / lines, s);
     return e == hipSuccess ? MW_OK : MW_EDEVICE;
   }
-  const u32 log_n1 = P->log_n1, log_n2 = P->log2n - P->log_n1;
-  const u32 col_tiles = (1u << log_n2) / kColLines;
-  const u32 row_tiles = (1u << log_n1) / kRowLines;
+  const u32 col_tiles = tiles_per_poly<MODE_COL>(P->log2n, P->log_n1, P->cfg[MODE_COL].lines);
+  const u32 row_tiles = tiles_per_poly<MODE_ROW>(P->log2n, P->log_n1, P->cfg[MODE_ROW].lines);
   const uint32_t chunk = P->scratch_polys;
   for (uint32_t b0 = 0; b0 < batch; b0 += chunk) {
     const uint32_t nb = (batch - b0 < chunk) ? batch - b0 : chunk;
@@ -533,22 +153,22 @@ int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, 
       p.src = in;
       p.dst = scr;
       p.permute = 0;
-      e = launch_by_log<W, DIR_FWD, MODE_COL>(log_n1, p, nb * col_tiles, s);
+      e = launch_pass<W>(dir, MODE_COL, P, p, nb * col_tiles, s);
       if (e != hipSuccess) break;
       p.src = scr;
       p.dst = out;
       p.permute = !(P->flags & NTT_BITREV_OUT);
-      e = launch_by_log<W, DIR_FWD, MODE_ROW>(log_n2, p, nb * row_tiles, s);
+      e = launch_pass<W>(dir, MODE_ROW, P, p, nb * row_tiles, s);
     } else {
       p.src = in;
       p.dst = scr;
       p.permute = !(P->flags & NTT_BITREV_IN);
-      e = launch_by_log<W, DIR_INV, MODE_ROW>(log_n2, p, nb * row_tiles, s);
+      e = launch_pass<W>(dir, MODE_ROW, P, p, nb * row_tiles, s);
       if (e != hipSuccess) break;
       p.src = scr;
       p.dst = out;
       p.permute = 0;
-      e = launch_by_log<W, DIR_INV, MODE_COL>(log_n1, p, nb * col_tiles, s);
+      e = launch_pass<W>(dir, MODE_COL, P, p, nb * col_tiles, s);
     }
     if (e != hipSuccess) break;
   }
@@ -571,6 +191,50 @@ uint32_t default_split(uint32_t log2n, uint32_t limbs) {
   return log2n / 2;
 }
 
+// Largest workgroup a tile kernel of this shape is compiled for (max_threads).
+uint32_t thread_bound(uint32_t logl, uint32_t logp) {
+  const uint32_t tpl = 1u << (logl - logp);
+  return tpl > 256 ? (tpl > 1024 ? 1024 : tpl) : 256;
+}
+
+// Threads, LDS and shape limits of a tile configuration (see shape_ok).
+bool tile_ok(uint32_t limbs, int mode, uint32_t logl, uint32_t logp, uint32_t lines, uint32_t max_lines) {
+  if (logp < 1 || logp > 4 || logp > logl || logl - logp > 10) return false;
+  if (mode == MODE_FULL) {
+    if (logl < 1 || logl > (limbs == 2 ? (uint32_t)kMaxFullLog4 : (uint32_t)kMaxFullLog2)) return false;
+  } else if (logl < 3 || logl > 9) {
+    return false;
+  }
+  if (lines == 0 || (lines & (lines - 1)) || lines > max_lines) return false;
+  if (lines * (1u << (logl - logp)) > thread_bound(logl, logp)) return false;
+  const size_t lds = limbs == 2 ? tile_lds_bytes<4>(logl, logp, lines) : tile_lds_bytes<2>(logl, logp, lines);
+  return lds <= 160 * 1024;
+}
+
+// Default tile shapes: 8 points per lane; full tiles fill 256 lanes (or one
+// line); column / row tiles take up to 8 lines (128-byte runs for two-word
+// moduli) within the kernel's thread bound.
+void default_pass(PassCfg& c, uint32_t logl, uint32_t max_lines) {
+  c.logp = logl < 3 ? logl : 3;
+  const uint32_t tpl = 1u << (logl - c.logp);
+  uint32_t lines = 8;
+  while (lines > 1 && (lines * tpl > thread_bound(logl, c.logp) || lines > max_lines)) lines >>= 1;
+  c.lines = lines;
+}
+
+void default_tiles(ntt_plan_s* P) {
+  const uint32_t logn = P->log2n;
+  uint32_t lp = logn < 3 ? logn : 3;
+  uint32_t tpl = 1u << (logn - lp);
+  while (tpl > 1024) { ++lp; tpl >>= 1; }
+  P->cfg[MODE_FULL].logp = lp;
+  P->cfg[MODE_FULL].lines = tpl >= 256 ? 1 : 256 / tpl;
+  if (P->log_n1) {
+    const uint32_t l1 = P->log_n1, l2 = logn - P->log_n1;
+    default_pass(P->cfg[MODE_COL], l1, 1u << l2);
+    default_pass(P->cfg[MODE_ROW], l2, 1u << l1);
+  }
+}
 }  // namespace
 
 extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint32_t limbs,
@@ -612,6 +276,7 @@ extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint
     return st;
   }
   P->log_n1 = default_split(log2n, limbs);
+  default_tiles(P);
   if (P->log_n1) {
     const size_t poly_bytes = (size_t)8 * limbs * n;
     size_t polys = kScratchBytes / poly_bytes;
@@ -644,6 +309,33 @@ extern "C" int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1) {
     plan->scratch_polys = (uint32_t)polys;
   }
   plan->log_n1 = log_n1;
+  default_tiles(plan);
+  return MW_OK;
+}
+
+extern "C" int ntt_plan_set_tiles(ntt_plan_t plan, uint32_t pass, uint32_t log_p, uint32_t lines) {
+  if (!plan || pass > 2) return MW_EINVAL;
+  const uint32_t logn = plan->log2n;
+  uint32_t logl, max_lines;
+  if (pass == MODE_FULL) {
+    if (plan->log_n1) return MW_EINVAL;
+    logl = logn;
+    max_lines = 1u << 16;
+  } else {
+    if (!plan->log_n1) return MW_EINVAL;
+    logl = pass == MODE_COL ? plan->log_n1 : logn - plan->log_n1;
+    max_lines = 1u << (pass == MODE_COL ? logn - plan->log_n1 : plan->log_n1);
+  }
+  if (!tile_ok(plan->limbs, (int)pass, logl, log_p, lines, max_lines)) return MW_EINVAL;
+  plan->cfg[pass].logp = log_p;
+  plan->cfg[pass].lines = lines;
+  return MW_OK;
+}
+
+extern "C" int ntt_plan_get_tiles(ntt_plan_t plan, uint32_t pass, uint32_t* log_p, uint32_t* lines) {
+  if (!plan || pass > 2 || !log_p || !lines) return MW_EINVAL;
+  *log_p = plan->cfg[pass].logp;
+  *lines = plan->cfg[pass].lines;
   return MW_OK;
 }
 

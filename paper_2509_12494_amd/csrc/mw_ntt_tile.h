@@ -1,0 +1,377 @@
+// Negacyclic NTT / INTT tiles over Z_q[X]/(X^N + 1) for gfx950.
+//
+// What is computed (Background, polynomial multiplication using NTT, Eq. ntt):
+//   forward  A_k = sum_j a_j psi^(j(2k+1))             (Eq. ntt on a_j psi^j,
+//   inverse  a_j = N^-1 psi^-j sum_k A_k psi^(-2jk)      omega_N = psi^2)
+// An N-point transform is log N stages of N/2 butterflies, each one modular
+// multiplication, one addition and one subtraction (SIMD-vectorized kernels,
+// from arithmetic to cryptographic kernels).
+//
+// Algorithm.  The forward transform is the merged-psi Cooley-Tukey form:
+// stage s (m = 2^s groups, half-width t = N/2m) pairs j and j+t and
+// multiplies by tw[m + floor(j/2t)], tw[i] = psi^bitrev(i), leaving the output
+// in bit-reversed order.  The inverse is the Gentleman-Sande form with
+// tw'[i] = psi^-bitrev(i), processing the stages in reverse and taking
+// bit-reversed input; N^-1 is folded into its last stage.  Butterflies are
+// lazy (Harvey): forward values stay in [0, 16q), inverse values in [0, 8q),
+// with one conditional subtraction per butterfly; results are made canonical
+// once at the end.
+//
+// Data movement (the paper permutes between stages with AVX-512 unpack /
+// permute instructions; here stages exchange data through LDS):
+//   * a "line" is an n = 2^LOGL point sub-transform held by n/P lanes, each lane
+//     owning P = 2^LOGP points; LOGP stages run in registers per round, and
+//     lanes exchange points through LDS between rounds;
+//   * small N: one line per transform, the whole transform in one workgroup
+//     ("full" tiles);
+//   * larger N: N = N1 * N2 and two passes over device memory.  The first
+//     log N1 Cooley-Tukey stages only pair elements in the same residue class
+//     mod N2 (columns of stride N2) and use the table entries below N1, so a
+//     column is an N1-point line with twiddle base 1.  The remaining log N2
+//     stages act within contiguous rows of N2 elements; row b is an N2-point
+//     line whose local stage m' uses tw[m' * (N1 + b) + g].  No transpose and
+//     no extra twiddle pass are needed.  The inverse runs the rows first, then
+//     the columns.
+//   * natural-order output of the forward transform: row b, local index l
+//     holds A at k = bitrev(l)*N1 + bitrev(b).  A row tile takes G rows
+//     b = j*(N1/G) + b_lo, whose outputs land in runs of G consecutive
+//     residues, so the permuted store (and the inverse's permuted load) is
+//     coalesced in G-residue segments.
+// The number of lines per tile (columns, rows or whole transforms) is a
+// launch-time choice; the points per lane P is a template parameter.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mw_arith.h"
+
+namespace mw {
+
+template <int W>
+struct Tw {
+  u32 w[W];
+  u32 ws[W];
+};
+
+template <int W>
+__device__ __forceinline__ Tw<W> load_tw(const Tw<W>* t, u32 idx) {
+  Tw<W> r;
+  if constexpr (W == 4) {
+    const uint4* p = reinterpret_cast<const uint4*>(t + idx);
+    uint4 a = p[0], b = p[1];
+    r.w[0] = a.x; r.w[1] = a.y; r.w[2] = a.z; r.w[3] = a.w;
+    r.ws[0] = b.x; r.ws[1] = b.y; r.ws[2] = b.z; r.ws[3] = b.w;
+  } else {
+    uint4 a = *reinterpret_cast<const uint4*>(t + idx);
+    r.w[0] = a.x; r.w[1] = a.y;
+    r.ws[0] = a.z; r.ws[1] = a.w;
+  }
+  return r;
+}
+
+enum { DIR_FWD = 0, DIR_INV = 1 };
+enum { MODE_FULL = 0, MODE_COL = 1, MODE_ROW = 2 };
+
+template <int W>
+struct NttParams {
+  const Res<W>* src;     // input of this pass
+  Res<W>* dst;           // output of this pass
+  const Tw<W>* tw;       // this direction's table, N entries
+  Modulus<W> M;
+  Tw<W> ninv;            // N^-1 and its Shoup companion (inverse only)
+  Tw<W> ninv_w1;         // tw'[1] * N^-1 (inverse only)
+  u32 log_n;             // transform size
+  u32 log_n1;            // rows of the two-pass split (N1 = 2^log_n1)
+  u32 batch;             // transforms in this launch
+  u32 permute;           // 1: natural order at the device-memory side of this pass
+  u32 lines;             // lines per tile (a power of two)
+  u32 pad_[3];
+};
+
+// Forward (Cooley-Tukey) butterfly on [0, 16q) values.
+template <int W>
+__device__ __forceinline__ void ct_bfly(Res<W>& X, Res<W>& Y, const Tw<W>& t, const Modulus<W>& M) {
+  Res<W> T = shoup_mul(Y, t.w, t.ws, M);   // [0, 6q)
+  Res<W> Xr = csub(X, M.q8);               // [0, 8q)
+  X = add(Xr, T);                          // [0, 14q)
+  Res<W> D = add(Xr, M.q8);                // [8q, 16q)
+  u32 b;
+  Y = sub(D, T, b);                        // (2q, 16q)
+}
+
+// Inverse (Gentleman-Sande) butterfly on [0, 8q) values.
+template <int W>
+__device__ __forceinline__ void gs_bfly(Res<W>& X, Res<W>& Y, const Tw<W>& t, const Modulus<W>& M) {
+  Res<W> S = csub(add(X, Y), M.q8);        // [0, 8q)
+  Res<W> D = add(X, M.q8);
+  u32 b;
+  D = sub(D, Y, b);                        // (0, 16q)
+  Y = shoup_mul(D, t.w, t.ws, M);          // [0, 6q)
+  X = S;
+}
+
+// Last inverse stage with N^-1 folded in; outputs canonical.
+template <int W>
+__device__ __forceinline__ void gs_bfly_last(Res<W>& X, Res<W>& Y, const Tw<W>& ninv, const Tw<W>& ninv_w1,
+                                             const Modulus<W>& M) {
+  Res<W> S = add(X, Y);                    // [0, 16q) < 2^(32W)
+  Res<W> D = add(X, M.q8);
+  u32 b;
+  D = sub(D, Y, b);                        // (0, 16q)
+  Res<W> x = shoup_mul(S, ninv.w, ninv.ws, M);     // [0, 6q)
+  Res<W> y = shoup_mul(D, ninv_w1.w, ninv_w1.ws, M);
+  x = csub(csub(csub(x, M.q4), M.q2), M.q);
+  y = csub(csub(csub(y, M.q4), M.q2), M.q);
+  X = x;
+  Y = y;
+}
+
+template <int W>
+__device__ __forceinline__ Res<W> canon16(const Res<W>& x, const Modulus<W>& M) {
+  return csub(csub(csub(csub(x, M.q8), M.q4), M.q2), M.q);
+}
+
+__device__ __forceinline__ u32 brev(u32 x, u32 bits) {
+  return bits ? (__builtin_bitreverse32(x) >> (32 - bits)) : 0u;
+}
+
+template <int LOGL, int LOGP>
+struct LineShape {
+  static constexpr int L = 1 << LOGL;
+  static constexpr int P = 1 << LOGP;
+  static constexpr int TPL = L / P;                      // lanes per line
+  // line stride in LDS: one padding slot per P points, plus one so that the
+  // same point of consecutive lines falls in different banks
+  static constexpr int NPAD = ((LOGL > LOGP) ? L + L / P : L) + 1;
+  static constexpr int R = (LOGL + LOGP - 1) / LOGP;     // rounds
+  static constexpr int P0 = LOGL - LOGP * (R - 1);       // stages in round 0
+};
+
+// LDS slot of point j within a line: one padding slot after every P points.
+template <int LOGL, int LOGP>
+__device__ __forceinline__ u32 pad_idx(u32 j) {
+  if constexpr (LOGL > LOGP) return j + (j >> LOGP);
+  else return j;
+}
+
+// One round of a line: LOGP (or, for round 0, the remainder P0) stages on the
+// P points a lane holds, between an LDS load and an LDS store.  In round r the
+// lane's point u sits at line index base_j | (u << L0), L0 = LOGL - s0 - LOGP;
+// the stages of the round pair the top np bits of u.  Rounds and stages are
+// compile-time recursions so every register index is a constant.
+template <int W, int LOGL, int LOGP, int DIR, int RIDX>
+struct Round {
+  using S = LineShape<LOGL, LOGP>;
+  static constexpr int P = S::P;
+  static constexpr int s0 = (RIDX == 0) ? 0 : S::P0 + (RIDX - 1) * LOGP;
+  static constexpr int np = (RIDX == 0) ? S::P0 : LOGP;
+  static constexpr int L0 = LOGL - s0 - LOGP;
+
+  template <int ST0>
+  static __device__ __forceinline__ void stage(Res<W> (&x)[P], u32 base_j, u32 base, const Tw<W>* __restrict__ tw,
+                                               const NttParams<W>& p, bool last_inv) {
+    constexpr int st = (DIR == DIR_FWD) ? ST0 : (np - 1 - ST0);
+    constexpr int s = s0 + st;              // stage index within the line
+    constexpr int ib = LOGP - 1 - st;       // bit of u that the stage pairs
+    constexpr int ngroups = 1 << st;        // distinct twiddles of the stage
+#pragma unroll
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const u32 j0 = base_j | ((u32)(gi << (ib + 1)) << L0);
+      const u32 g = j0 >> (LOGL - s);
+      if (DIR == DIR_INV && s == 0 && last_inv) {
+#pragma unroll
+        for (int lo = 0; lo < (1 << ib); ++lo) {
+          const int u = (gi << (ib + 1)) | lo;
+          gs_bfly_last(x[u], x[u | (1 << ib)], p.ninv, p.ninv_w1, p.M);
+        }
+      } else {
+        const Tw<W> t = load_tw(tw, (base << s) + g);
+#pragma unroll
+        for (int lo = 0; lo < (1 << ib); ++lo) {
+          const int u = (gi << (ib + 1)) | lo;
+          if (DIR == DIR_FWD) ct_bfly(x[u], x[u | (1 << ib)], t, p.M);
+          else gs_bfly(x[u], x[u | (1 << ib)], t, p.M);
+        }
+      }
+    }
+    if constexpr (ST0 + 1 < np) stage<ST0 + 1>(x, base_j, base, tw, p, last_inv);
+  }
+
+  static __device__ __forceinline__ void run(Res<W>* line, u32 tid, u32 base, const Tw<W>* __restrict__ tw,
+                                             const NttParams<W>& p, bool last_inv, bool canon) {
+    const u32 base_j = ((tid >> L0) << (L0 + LOGP)) | (tid & ((1u << L0) - 1u));
+    Res<W> x[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) x[u] = line[pad_idx<LOGL, LOGP>(base_j | ((u32)u << L0))];
+    stage<0>(x, base_j, base, tw, p, last_inv);
+    if (canon) {
+#pragma unroll
+      for (int u = 0; u < P; ++u) x[u] = canon16(x[u], p.M);
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) line[pad_idx<LOGL, LOGP>(base_j | ((u32)u << L0))] = x[u];
+    __syncthreads();
+  }
+};
+
+// All rounds of a line held in LDS (forward: rounds 0..R-1; inverse: R-1..0).
+// tid: lane index within the line; base: twiddle base (1, or N1 + b for rows);
+// last_inv: the line contains the final inverse stage (fold N^-1);
+// final_fwd: canonicalize after the last forward stage.
+template <int W, int LOGL, int LOGP, int DIR, int RR = 0>
+__device__ __forceinline__ void line_stages(Res<W>* line, u32 tid, u32 base, const Tw<W>* __restrict__ tw,
+                                            const NttParams<W>& p, bool last_inv, bool final_fwd) {
+  using S = LineShape<LOGL, LOGP>;
+  constexpr int R = (DIR == DIR_FWD) ? RR : (S::R - 1 - RR);
+  Round<W, LOGL, LOGP, DIR, R>::run(line, tid, base, tw, p, last_inv,
+                                    DIR == DIR_FWD && final_fwd && RR == S::R - 1);
+  if constexpr (RR + 1 < S::R) line_stages<W, LOGL, LOGP, DIR, RR + 1>(line, tid, base, tw, p, last_inv, final_fwd);
+}
+
+// Number of tiles one launch of a pass covers.
+template <int MODE>
+__host__ __device__ inline u32 tiles_per_poly(u32 log_n, u32 log_n1, u32 lines) {
+  if (MODE == MODE_COL) return (1u << (log_n - log_n1)) / lines;
+  if (MODE == MODE_ROW) return (1u << log_n1) / lines;
+  return 1;
+}
+
+// One tile: device memory -> LDS, the line stages, LDS -> device memory.
+// All threads of the workgroup take part (lines * L/P threads); `lds` holds
+// lines * NPAD residues.  For MODE_FULL, `tile` indexes groups of `lines`
+// transforms; otherwise it indexes (poly, tile-within-poly).
+template <int W, int LOGL, int LOGP, int DIR, int MODE>
+__device__ __forceinline__ void ntt_tile(const NttParams<W>& p, Res<W>* lds, u32 tile) {
+  using S = LineShape<LOGL, LOGP>;
+  constexpr int L = S::L;
+  const u32 lines = p.lines;
+  const u32 T = lines * S::TPL;
+  const u32 t = threadIdx.x;
+  const u32 line_id = t / S::TPL;
+  const u32 lane = t % S::TPL;
+  const u32 log_n = p.log_n;
+  const u64 N = (u64)1 << log_n;
+  const u32 log_lines = __builtin_ctz(lines);
+  const u32 nelem = lines << LOGL;
+
+  u32 poly;
+  u32 c0 = 0, b_lo = 0;
+  const u32 log_n1 = p.log_n1, log_n2 = log_n - p.log_n1;
+  if (MODE == MODE_FULL) {
+    poly = tile;   // group of `lines` transforms
+  } else {
+    const u32 tiles = tiles_per_poly<MODE>(log_n, log_n1, lines);
+    poly = tile / tiles;
+    if (MODE == MODE_COL) c0 = (tile % tiles) * lines;
+    else b_lo = tile % tiles;
+  }
+
+  // ---- device memory -> LDS ----
+  if (MODE == MODE_FULL) {
+    for (u32 e = t; e < nelem; e += T) {
+      const u32 ln = e >> LOGL, j = e & (L - 1);
+      const u64 pl = (u64)poly * lines + ln;
+      if (pl < p.batch) {
+        const u32 dj = (DIR == DIR_INV && p.permute) ? brev(j, LOGL) : j;
+        lds[ln * S::NPAD + pad_idx<LOGL, LOGP>(dj)] = ResIO<W>::load(p.src + pl * N + j);
+      }
+    }
+  } else if (MODE == MODE_COL) {
+    const u64 N2 = (u64)1 << log_n2;
+    for (u32 e = t; e < nelem; e += T) {
+      const u32 r = e >> log_lines, c = e & (lines - 1);
+      lds[c * S::NPAD + pad_idx<LOGL, LOGP>(r)] = ResIO<W>::load(p.src + (u64)poly * N + r * N2 + c0 + c);
+    }
+  } else {
+    const u32 n1_over_g = (1u << log_n1) >> log_lines;
+    if (DIR == DIR_INV && p.permute) {
+      // natural-order input: run of G residues at k = l'*N1 + bitrev(b_lo)*G + jj
+      const u32 col = brev(b_lo, log_n1 - log_lines) << log_lines;
+      for (u32 e = t; e < nelem; e += T) {
+        const u32 lp = e >> log_lines, jj = e & (lines - 1);
+        const u64 src = (u64)poly * N + ((u64)lp << log_n1) + col + jj;
+        lds[brev(jj, log_lines) * S::NPAD + pad_idx<LOGL, LOGP>(brev(lp, LOGL))] = ResIO<W>::load(p.src + src);
+      }
+    } else {
+      for (u32 e = t; e < nelem; e += T) {
+        const u32 j = e >> LOGL, l = e & (L - 1);
+        const u32 b = j * n1_over_g + b_lo;
+        lds[j * S::NPAD + pad_idx<LOGL, LOGP>(l)] = ResIO<W>::load(p.src + (u64)poly * N + ((u64)b << LOGL) + l);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- stages ----
+  u32 base = 1;
+  if (MODE == MODE_ROW) base = (1u << log_n1) + line_id * ((1u << log_n1) >> log_lines) + b_lo;
+  const bool last_inv = (DIR == DIR_INV) && (MODE != MODE_ROW);
+  const bool final_fwd = (DIR == DIR_FWD) && (MODE != MODE_COL);
+  line_stages<W, LOGL, LOGP, DIR>(lds + line_id * S::NPAD, lane, base, p.tw, p, last_inv, final_fwd);
+
+  // ---- LDS -> device memory ----
+  if (MODE == MODE_FULL) {
+    for (u32 e = t; e < nelem; e += T) {
+      const u32 ln = e >> LOGL, j = e & (L - 1);
+      const u64 pl = (u64)poly * lines + ln;
+      if (pl < p.batch) {
+        const u32 sj = (DIR == DIR_FWD && p.permute) ? brev(j, LOGL) : j;
+        ResIO<W>::store(p.dst + pl * N + j, lds[ln * S::NPAD + pad_idx<LOGL, LOGP>(sj)]);
+      }
+    }
+  } else if (MODE == MODE_COL) {
+    const u64 N2 = (u64)1 << log_n2;
+    for (u32 e = t; e < nelem; e += T) {
+      const u32 r = e >> log_lines, c = e & (lines - 1);
+      ResIO<W>::store(p.dst + (u64)poly * N + r * N2 + c0 + c, lds[c * S::NPAD + pad_idx<LOGL, LOGP>(r)]);
+    }
+  } else {
+    const u32 n1_over_g = (1u << log_n1) >> log_lines;
+    if (DIR == DIR_FWD && p.permute) {
+      const u32 col = brev(b_lo, log_n1 - log_lines) << log_lines;
+      for (u32 e = t; e < nelem; e += T) {
+        const u32 lp = e >> log_lines, jj = e & (lines - 1);
+        const u64 dst = (u64)poly * N + ((u64)lp << log_n1) + col + jj;
+        ResIO<W>::store(p.dst + dst, lds[brev(jj, log_lines) * S::NPAD + pad_idx<LOGL, LOGP>(brev(lp, LOGL))]);
+      }
+    } else {
+      for (u32 e = t; e < nelem; e += T) {
+        const u32 j = e >> LOGL, l = e & (L - 1);
+        const u32 b = j * n1_over_g + b_lo;
+        ResIO<W>::store(p.dst + (u64)poly * N + ((u64)b << LOGL) + l, lds[j * S::NPAD + pad_idx<LOGL, LOGP>(l)]);
+      }
+    }
+  }
+}
+
+// Largest workgroup a tile kernel of this shape is compiled for.
+template <int LOGL, int LOGP>
+constexpr int max_threads() {
+  constexpr int tpl = 1 << (LOGL - LOGP);
+  return tpl > 256 ? (tpl > 1024 ? 1024 : tpl) : 256;
+}
+
+// Kernel shapes that are instantiated: full transforms of 2^1..2^12 points
+// (2^13 for one-word moduli); column / row lines of 2^3..2^9 points; points per
+// lane 2^1..2^4 with at most 1024 lanes per line.
+template <int W, int MODE>
+constexpr bool shape_ok(int logl, int logp) {
+  if (logp < 1 || logp > 4 || logp > logl) return false;
+  if (logl - logp > 10) return false;
+  if (MODE == MODE_FULL) return logl >= 1 && logl <= (W == 4 ? 12 : 13);
+  return logl >= 3 && logl <= 9;
+}
+
+extern "C++" {
+template <int W, int DIR>
+hipError_t launch_ntt(int mode, u32 logl, u32 logp, const NttParams<W>& p, u32 blocks, hipStream_t s);
+}
+
+// Dynamic LDS bytes of a tile.
+template <int W>
+inline size_t tile_lds_bytes(u32 logl, u32 logp, u32 lines) {
+  const u32 L = 1u << logl, P = 1u << logp;
+  const u32 npad = ((logl > logp) ? L + L / P : L) + 1;
+  return (size_t)lines * npad * sizeof(Res<W>);
+}
+
+}  // namespace mw

@@ -53,6 +53,8 @@ def lib() -> ctypes.CDLL:
         "ntt_plan_root": (ctypes.c_int, [vp, u64p]),
         "ntt_plan_set_split": (ctypes.c_int, [vp, u32]),
         "ntt_plan_get_split": (ctypes.c_int, [vp, ctypes.POINTER(u32)]),
+        "ntt_plan_set_tiles": (ctypes.c_int, [vp, u32, u32, u32]),
+        "ntt_plan_get_tiles": (ctypes.c_int, [vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
         "ntt_forward": (ctypes.c_int, [vp, vp, vp, u32, vp]),
         "ntt_inverse": (ctypes.c_int, [vp, vp, vp, u32, vp]),
         "mw_canonical_root": (ctypes.c_int, [u64p, u32, u32, u64p]),
@@ -179,6 +181,16 @@ class NttPlan:
     @split.setter
     def split(self, log_n1: int) -> None:
         _check(lib().ntt_plan_set_split(self._h, log_n1), "ntt_plan_set_split")
+
+    PASS_FULL, PASS_COL, PASS_ROW = 0, 1, 2
+
+    def set_tiles(self, pass_: int, log_p: int, lines: int) -> None:
+        _check(lib().ntt_plan_set_tiles(self._h, pass_, log_p, lines), "ntt_plan_set_tiles")
+
+    def get_tiles(self, pass_: int):
+        lp, ln = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().ntt_plan_get_tiles(self._h, pass_, ctypes.byref(lp), ctypes.byref(ln)), "ntt_plan_get_tiles")
+        return lp.value, ln.value
 
     def _batch(self, t, batch):
         if batch is not None:

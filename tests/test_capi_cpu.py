@@ -106,3 +106,10 @@ def test_argument_errors_without_device():
     with pytest.raises(mwntt.MwError) as e:
         mwntt.vec_axpymod(8, q60, 8, q60, 1, n=5, stream=0)  # alpha not reduced
     assert e.value.status == -1
+
+
+def test_tile_argument_errors_without_device():
+    # set_tiles on a null plan is rejected before any device work
+    L = mwntt.lib()
+    assert L.ntt_plan_set_tiles(None, 1, 3, 8) == -1
+    assert L.ntt_plan_set_split(None, 4) == -1
