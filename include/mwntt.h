@@ -111,8 +111,12 @@ int ntt_plan_root(ntt_plan_t plan, uint64_t* psi_out);
  * log_n1 == 0 runs each transform in one workgroup (N <= 2^12 for two-word
  * moduli, N <= 2^13 for one-word moduli); otherwise two passes over device
  * memory with N1 = 2^log_n1 rows and N2 = N / N1 columns, 3 <= log2(N1),
- * log2(N2) <= 9.  Results do not depend on the split.  Not thread-safe with
- * concurrent transforms on the same plan. */
+ * log2(N2) <= 9.  By default a plan holds two measured configurations, one
+ * for calls with little work (a single transform spread over as many CUs as
+ * possible) and one for large batches, and picks per call; setting a split
+ * or a tile shape replaces both for every later call.  get_* report the
+ * large-batch configuration unless one was set.  Results never depend on the
+ * configuration.  Not thread-safe with concurrent transforms on the plan. */
 int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1);
 int ntt_plan_get_split(ntt_plan_t plan, uint32_t* log_n1);
 

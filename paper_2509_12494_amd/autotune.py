@@ -121,14 +121,68 @@ def tune(log2n: int, bits: int, batch: int, reps: int = 10, seed: int = 7) -> di
             "candidates": len(results), "ranked": results[:12]}
 
 
+def emit_header(jsonl_paths, out_path: str) -> None:
+    """Write the tuned-configuration table (C header) from autotuner JSONL output.
+
+    Batch 1 results become the latency entries, the largest batch per
+    (width, N) the throughput entries."""
+    best = {}
+    for path in jsonl_paths:
+        for line in open(path):
+            r = json.loads(line)
+            key = (2 if r["bits"] > 60 else 1, r["log2n"])
+            kind = 0 if r["batch"] == 1 else 1
+            cur = best.get((key, kind))
+            if kind == 1 and cur is not None and cur[0] > r["batch"]:
+                continue
+            best[(key, kind)] = (r["batch"], r["best"]["cfg"], r["best"]["us_per_ntt"])
+    rows = []
+    for ((limbs, log2n), kind), (batch, cfg, us) in sorted(best.items()):
+        full = cfg.get("full", (0, 0))
+        col = cfg.get("col", (0, 0))
+        row = cfg.get("row", (0, 0))
+        rows.append(f"    {{{limbs}, {log2n}, {kind}, {cfg['split']}, {full[0]}, {full[1]}, {col[0]}, {col[1]}, "
+                    f"{row[0]}, {row[1]}}},  // batch {batch}: {us} us per transform")
+    text = """// Tuned NTT decompositions and tile shapes for MI355X (gfx950).
+// Generated by `python -m paper_2509_12494_amd.autotune ... --emit-header` from
+// measured sweeps (forward + inverse round trips, every candidate checked bit
+// for bit against the default configuration).  kind 0: latency (one
+// transform per call), kind 1: throughput (large batches).
+#pragma once
+#include <stdint.h>
+
+namespace mw {
+
+struct TunedCfg {
+  uint8_t limbs, log2n, kind, log_n1;
+  uint8_t full_logp;
+  uint16_t full_lines;
+  uint8_t col_logp, col_lines, row_logp, row_lines;
+};
+
+static const TunedCfg kTuned[] = {
+%s
+};
+
+}  // namespace mw
+""" % "\n".join(rows)
+    with open(out_path, "w") as f:
+        f.write(text)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
+    ap.add_argument("--emit-header", nargs=2, metavar=("JSONL", "HEADER"),
+                    help="write the tuned table from a sweep's JSONL instead of sweeping")
     ap.add_argument("--log2n", type=int, nargs="+", default=[16])
     ap.add_argument("--bits", type=int, nargs="+", default=[124])
     ap.add_argument("--batch", type=int, nargs="+", default=[1, 64])
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
+    if args.emit_header:
+        emit_header([args.emit_header[0]], args.emit_header[1])
+        return 0
     out = open(args.out, "a") if args.out else None
     for bits in args.bits:
         for log2n in args.log2n:

@@ -15,6 +15,7 @@
 #include "mw_arith.h"
 #include "mw_common.h"
 #include "mw_ntt_tile.h"
+#include "mw_tuned.h"
 
 namespace mw {
 constexpr int kMaxFullLog4 = 12;   // largest single-workgroup transform, two-word moduli
@@ -31,10 +32,19 @@ struct PassCfg {
   uint32_t lines = 8;         // lines per tile
 };
 
+struct PlanConfig {
+  uint32_t log_n1 = 0;        // 0: single-workgroup transform
+  PassCfg cfg[3];             // MODE_FULL, MODE_COL, MODE_ROW
+};
+
 struct ntt_plan_s {
   uint32_t log2n = 0, limbs = 0, flags = 0;
-  uint32_t log_n1 = 0;        // 0: single-tile transform
-  PassCfg cfg[3];             // MODE_FULL, MODE_COL, MODE_ROW
+  // Two configurations: `lat` for calls with little work (one or a few
+  // transforms: the shape that spreads one transform over the most CUs) and
+  // `thr` for large batches.  A caller-set split / shape (`forced`) applies to
+  // every call.
+  PlanConfig lat, thr;
+  bool forced = false;
   uint64_t q[2] = {0, 0};
   uint64_t psi[2] = {0, 0};
   int device = 0;
@@ -107,11 +117,20 @@ void free_plan(ntt_plan_s* P) {
 constexpr size_t kScratchBytes = size_t(64) << 20;
 
 template <int W>
-hipError_t launch_pass(int dir, int mode, const ntt_plan_s* P, NttParams<W>& p, u32 blocks, hipStream_t s) {
-  const u32 logl = mode == MODE_FULL ? P->log2n : (mode == MODE_COL ? P->log_n1 : P->log2n - P->log_n1);
-  p.lines = P->cfg[mode].lines;
-  return dir == DIR_FWD ? launch_ntt<W, DIR_FWD>(mode, logl, P->cfg[mode].logp, p, blocks, s)
-                        : launch_ntt<W, DIR_INV>(mode, logl, P->cfg[mode].logp, p, blocks, s);
+hipError_t launch_pass(int dir, int mode, const ntt_plan_s* P, const PlanConfig& C, NttParams<W>& p, u32 blocks,
+                       hipStream_t s) {
+  const u32 logl = mode == MODE_FULL ? P->log2n : (mode == MODE_COL ? C.log_n1 : P->log2n - C.log_n1);
+  p.lines = C.cfg[mode].lines;
+  return dir == DIR_FWD ? launch_ntt<W, DIR_FWD>(mode, logl, C.cfg[mode].logp, p, blocks, s)
+                        : launch_ntt<W, DIR_INV>(mode, logl, C.cfg[mode].logp, p, blocks, s);
+}
+
+// Calls moving at least this many residues use the throughput configuration.
+constexpr uint64_t kThroughputResidues = uint64_t(1) << 19;
+
+const PlanConfig& pick_config(const ntt_plan_s* P, uint32_t batch) {
+  if (P->forced) return P->lat;
+  return ((uint64_t)batch << P->log2n) >= kThroughputResidues ? P->thr : P->lat;
 }
 
 template <int W>
@@ -127,21 +146,22 @@ int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, 
     p.ninv = P->ninv2;
     p.ninv_w1 = P->last2;
   }
+  const PlanConfig& C = pick_config(P, batch);
   p.log_n = P->log2n;
-  p.log_n1 = P->log_n1;
+  p.log_n1 = C.log_n1;
   const uint64_t N = 1ull << P->log2n;
   hipError_t e = hipSuccess;
-  if (P->log_n1 == 0) {
+  if (C.log_n1 == 0) {
     p.src = reinterpret_cast<const Res<W>*>(d_in);
     p.dst = reinterpret_cast<Res<W>*>(d_out);
     p.batch = batch;
     p.permute = dir == DIR_FWD ? !(P->flags & NTT_BITREV_OUT) : !(P->flags & NTT_BITREV_IN);
-    const u32 lines = P->cfg[MODE_FULL].lines;
-    e = launch_pass<W>(dir, MODE_FULL, P, p, (batch + lines - 1) / lines, s);
+    const u32 lines = C.cfg[MODE_FULL].lines;
+    e = launch_pass<W>(dir, MODE_FULL, P, C, p, (batch + lines - 1) / lines, s);
     return e == hipSuccess ? MW_OK : MW_EDEVICE;
   }
-  const u32 col_tiles = tiles_per_poly<MODE_COL>(P->log2n, P->log_n1, P->cfg[MODE_COL].lines);
-  const u32 row_tiles = tiles_per_poly<MODE_ROW>(P->log2n, P->log_n1, P->cfg[MODE_ROW].lines);
+  const u32 col_tiles = tiles_per_poly<MODE_COL>(P->log2n, C.log_n1, C.cfg[MODE_COL].lines);
+  const u32 row_tiles = tiles_per_poly<MODE_ROW>(P->log2n, C.log_n1, C.cfg[MODE_ROW].lines);
   const uint32_t chunk = P->scratch_polys;
   for (uint32_t b0 = 0; b0 < batch; b0 += chunk) {
     const uint32_t nb = (batch - b0 < chunk) ? batch - b0 : chunk;
@@ -153,22 +173,22 @@ int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, 
       p.src = in;
       p.dst = scr;
       p.permute = 0;
-      e = launch_pass<W>(dir, MODE_COL, P, p, nb * col_tiles, s);
+      e = launch_pass<W>(dir, MODE_COL, P, C, p, nb * col_tiles, s);
       if (e != hipSuccess) break;
       p.src = scr;
       p.dst = out;
       p.permute = !(P->flags & NTT_BITREV_OUT);
-      e = launch_pass<W>(dir, MODE_ROW, P, p, nb * row_tiles, s);
+      e = launch_pass<W>(dir, MODE_ROW, P, C, p, nb * row_tiles, s);
     } else {
       p.src = in;
       p.dst = scr;
       p.permute = !(P->flags & NTT_BITREV_IN);
-      e = launch_pass<W>(dir, MODE_ROW, P, p, nb * row_tiles, s);
+      e = launch_pass<W>(dir, MODE_ROW, P, C, p, nb * row_tiles, s);
       if (e != hipSuccess) break;
       p.src = scr;
       p.dst = out;
       p.permute = 0;
-      e = launch_pass<W>(dir, MODE_COL, P, p, nb * col_tiles, s);
+      e = launch_pass<W>(dir, MODE_COL, P, C, p, nb * col_tiles, s);
     }
     if (e != hipSuccess) break;
   }
@@ -222,18 +242,52 @@ void default_pass(PassCfg& c, uint32_t logl, uint32_t max_lines) {
   c.lines = lines;
 }
 
-void default_tiles(ntt_plan_s* P) {
-  const uint32_t logn = P->log2n;
+void default_tiles(uint32_t logn, PlanConfig& C) {
   uint32_t lp = logn < 3 ? logn : 3;
   uint32_t tpl = 1u << (logn - lp);
   while (tpl > 1024) { ++lp; tpl >>= 1; }
-  P->cfg[MODE_FULL].logp = lp;
-  P->cfg[MODE_FULL].lines = tpl >= 256 ? 1 : 256 / tpl;
-  if (P->log_n1) {
-    const uint32_t l1 = P->log_n1, l2 = logn - P->log_n1;
-    default_pass(P->cfg[MODE_COL], l1, 1u << l2);
-    default_pass(P->cfg[MODE_ROW], l2, 1u << l1);
+  C.cfg[MODE_FULL].logp = lp;
+  C.cfg[MODE_FULL].lines = tpl >= 256 ? 1 : 256 / tpl;
+  if (C.log_n1) {
+    const uint32_t l1 = C.log_n1, l2 = logn - C.log_n1;
+    default_pass(C.cfg[MODE_COL], l1, 1u << l2);
+    default_pass(C.cfg[MODE_ROW], l2, 1u << l1);
   }
+}
+
+bool config_ok(uint32_t limbs, uint32_t logn, const PlanConfig& C) {
+  if (C.log_n1 == 0) return tile_ok(limbs, MODE_FULL, logn, C.cfg[MODE_FULL].logp, C.cfg[MODE_FULL].lines, 1u << 16);
+  const uint32_t l1 = C.log_n1, l2 = logn > l1 ? logn - l1 : 0;
+  return tile_ok(limbs, MODE_COL, l1, C.cfg[MODE_COL].logp, C.cfg[MODE_COL].lines, 1u << l2) &&
+         tile_ok(limbs, MODE_ROW, l2, C.cfg[MODE_ROW].logp, C.cfg[MODE_ROW].lines, 1u << l1);
+}
+
+// Default configurations, then the measured ones where the tuned table has
+// an entry for this (width, N).
+void initial_configs(ntt_plan_s* P) {
+  P->lat.log_n1 = default_split(P->log2n, P->limbs);
+  default_tiles(P->log2n, P->lat);
+  P->thr = P->lat;
+  for (const TunedCfg& t : kTuned) {
+    if (t.limbs != P->limbs || t.log2n != P->log2n) continue;
+    PlanConfig C;
+    C.log_n1 = t.log_n1;
+    C.cfg[MODE_FULL] = {t.full_logp, t.full_lines};
+    C.cfg[MODE_COL] = {t.col_logp, t.col_lines};
+    C.cfg[MODE_ROW] = {t.row_logp, t.row_lines};
+    if (!config_ok(P->limbs, P->log2n, C)) continue;
+    (t.kind == 0 ? P->lat : P->thr) = C;
+  }
+}
+
+int ensure_scratch(ntt_plan_s* P) {
+  if (P->d_scratch) return MW_OK;
+  const size_t poly_bytes = (size_t)8 * P->limbs << P->log2n;
+  size_t polys = kScratchBytes / poly_bytes;
+  if (polys < 1) polys = 1;
+  if (hipMalloc(&P->d_scratch, polys * poly_bytes) != hipSuccess) return MW_ENOMEM;
+  P->scratch_polys = (uint32_t)polys;
+  return MW_OK;
 }
 }  // namespace
 
@@ -275,16 +329,12 @@ extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint
     free_plan(P);
     return st;
   }
-  P->log_n1 = default_split(log2n, limbs);
-  default_tiles(P);
-  if (P->log_n1) {
-    const size_t poly_bytes = (size_t)8 * limbs * n;
-    size_t polys = kScratchBytes / poly_bytes;
-    if (polys < 1) polys = 1;
-    P->scratch_polys = (uint32_t)polys;
-    if (hipMalloc(&P->d_scratch, polys * poly_bytes) != hipSuccess) {
+  initial_configs(P);
+  if (P->lat.log_n1 || P->thr.log_n1) {
+    st = ensure_scratch(P);
+    if (st != MW_OK) {
       free_plan(P);
-      return MW_ENOMEM;
+      return st;
     }
   }
   *out = P;
@@ -296,52 +346,59 @@ extern "C" int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1) {
   const uint32_t max_full = plan->limbs == 2 ? kMaxFullLog4 : kMaxFullLog2;
   if (log_n1 == 0) {
     if (plan->log2n > max_full) return MW_ESIZE;
-    plan->log_n1 = 0;
-    return MW_OK;
+  } else {
+    const uint32_t log_n2 = plan->log2n > log_n1 ? plan->log2n - log_n1 : 0;
+    if (log_n1 < 3 || log_n1 > 9 || log_n2 < 3 || log_n2 > 9) return MW_ESIZE;
+    int st = ensure_scratch(plan);
+    if (st != MW_OK) return st;
   }
-  const uint32_t log_n2 = plan->log2n > log_n1 ? plan->log2n - log_n1 : 0;
-  if (log_n1 < 3 || log_n1 > 9 || log_n2 < 3 || log_n2 > 9) return MW_ESIZE;
-  if (!plan->d_scratch) {
-    const size_t poly_bytes = (size_t)8 * plan->limbs << plan->log2n;
-    size_t polys = kScratchBytes / poly_bytes;
-    if (polys < 1) polys = 1;
-    if (hipMalloc(&plan->d_scratch, polys * poly_bytes) != hipSuccess) return MW_ENOMEM;
-    plan->scratch_polys = (uint32_t)polys;
-  }
-  plan->log_n1 = log_n1;
-  default_tiles(plan);
+  plan->forced = true;
+  plan->lat.log_n1 = log_n1;
+  default_tiles(plan->log2n, plan->lat);
+  plan->thr = plan->lat;
   return MW_OK;
 }
 
+// The configuration a caller sees: the forced one, else the throughput one.
+static PlanConfig& visible_config(ntt_plan_t plan) { return plan->forced ? plan->lat : plan->thr; }
+
 extern "C" int ntt_plan_set_tiles(ntt_plan_t plan, uint32_t pass, uint32_t log_p, uint32_t lines) {
   if (!plan || pass > 2) return MW_EINVAL;
+  PlanConfig C = visible_config(plan);
   const uint32_t logn = plan->log2n;
   uint32_t logl, max_lines;
   if (pass == MODE_FULL) {
-    if (plan->log_n1) return MW_EINVAL;
+    if (C.log_n1) return MW_EINVAL;
     logl = logn;
     max_lines = 1u << 16;
   } else {
-    if (!plan->log_n1) return MW_EINVAL;
-    logl = pass == MODE_COL ? plan->log_n1 : logn - plan->log_n1;
-    max_lines = 1u << (pass == MODE_COL ? logn - plan->log_n1 : plan->log_n1);
+    if (!C.log_n1) return MW_EINVAL;
+    logl = pass == MODE_COL ? C.log_n1 : logn - C.log_n1;
+    max_lines = 1u << (pass == MODE_COL ? logn - C.log_n1 : C.log_n1);
   }
   if (!tile_ok(plan->limbs, (int)pass, logl, log_p, lines, max_lines)) return MW_EINVAL;
-  plan->cfg[pass].logp = log_p;
-  plan->cfg[pass].lines = lines;
+  if (C.log_n1) {
+    int st = ensure_scratch(plan);
+    if (st != MW_OK) return st;
+  }
+  C.cfg[pass].logp = log_p;
+  C.cfg[pass].lines = lines;
+  plan->forced = true;
+  plan->lat = plan->thr = C;
   return MW_OK;
 }
 
 extern "C" int ntt_plan_get_tiles(ntt_plan_t plan, uint32_t pass, uint32_t* log_p, uint32_t* lines) {
   if (!plan || pass > 2 || !log_p || !lines) return MW_EINVAL;
-  *log_p = plan->cfg[pass].logp;
-  *lines = plan->cfg[pass].lines;
+  const PlanConfig& C = visible_config(plan);
+  *log_p = C.cfg[pass].logp;
+  *lines = C.cfg[pass].lines;
   return MW_OK;
 }
 
 extern "C" int ntt_plan_get_split(ntt_plan_t plan, uint32_t* log_n1) {
   if (!plan || !log_n1) return MW_EINVAL;
-  *log_n1 = plan->log_n1;
+  *log_n1 = visible_config(plan).log_n1;
   return MW_OK;
 }
 
