@@ -137,6 +137,47 @@ int ntt_forward(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, 
 int ntt_inverse(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batched executor: many jobs -- forward or inverse transforms, or fused     */
+/* negacyclic products c = INTT(NTT(a) * NTT(b)) (Background, polynomial     */
+/* multiplication using NTT; the schoolbook product reduced mod X^N + 1) --  */
+/* of any mix of lengths (2^6 .. 2^17) and modulus widths, run as one kernel */
+/* launch per phase (two for transforms, three when a product is present),   */
+/* each launch covering every job.                                           */
+/* ------------------------------------------------------------------------ */
+typedef struct ntt_batch_s* ntt_batch_t;
+
+enum ntt_job_op { NTT_JOB_FORWARD = 0, NTT_JOB_INVERSE = 1, NTT_JOB_POLYMUL = 2 };
+
+/* One job.  plan gives q, N, width, root and the order flags (NTT_BITREV_OUT
+ * applies to forward outputs, NTT_BITREV_IN to inverse inputs; products take
+ * and return natural order).  in / in2 / out are device buffers of N
+ * residues; in2 is used by NTT_JOB_POLYMUL only (b; in is a).  out may alias
+ * in or in2.  Products need the Barrett width rule of vec_mulmod. */
+typedef struct {
+  ntt_plan_t plan;
+  uint32_t op;
+  const void* in;
+  const void* in2;
+  void* out;
+} ntt_job;
+
+/* Builds the device job list, tile list and scratch (N residues per
+ * transform, 2N per product).  Synchronous.  The plans must outlive the
+ * batch, and the job buffers must stay allocated at the same addresses for
+ * every run. */
+int ntt_batch_create(ntt_batch_t* batch, const ntt_job* jobs, uint32_t count);
+/* Runs every job: 2 or 3 kernel launches on `stream`, no allocation and no
+ * memset, so a run can be captured in a hipGraph and replayed.  Runs of one
+ * batch must not overlap in time (they share the batch's scratch). */
+int ntt_batch_run(ntt_batch_t batch, void* stream);
+/* Tiles in the batch and launches per run (either pointer may be NULL). */
+int ntt_batch_info(ntt_batch_t batch, uint32_t* tiles, uint32_t* launches);
+/* Synchronizes the device; MW_EDEVICE if a previous launch failed. */
+int ntt_batch_check(ntt_batch_t batch);
+/* Frees the batch (synchronizes the device first). */
+int ntt_batch_destroy(ntt_batch_t batch);
+
+/* ------------------------------------------------------------------------ */
 /* Host-only helpers (no device needed): the plan's own arithmetic, exposed */
 /* for inspection.                                                           */
 /* ------------------------------------------------------------------------ */

@@ -291,6 +291,34 @@ int ensure_scratch(ntt_plan_s* P) {
 }
 }  // namespace
 
+namespace mw {
+struct PlanView {
+  uint32_t log2n, limbs, flags;
+  const uint64_t* q;
+  const void* tw_fwd;
+  const void* tw_inv;
+};
+
+// Read access to a plan for the batched executor (mw_exec.hip).
+bool plan_view(const ntt_plan_s* P, PlanView& v, Modulus<4>& m4, Tw<4>& n4, Tw<4>& l4, Modulus<2>& m2, Tw<2>& n2,
+               Tw<2>& l2) {
+  if (!P) return false;
+  v.log2n = P->log2n;
+  v.limbs = P->limbs;
+  v.flags = P->flags;
+  v.q = P->q;
+  v.tw_fwd = P->d_tw_fwd;
+  v.tw_inv = P->d_tw_inv;
+  m4 = P->M4;
+  n4 = P->ninv4;
+  l4 = P->last4;
+  m2 = P->M2;
+  n2 = P->ninv2;
+  l2 = P->last2;
+  return true;
+}
+}  // namespace mw
+
 extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint32_t limbs,
                         const uint64_t* psi, uint32_t flags) {
   if (!out) return MW_EINVAL;

@@ -1,0 +1,247 @@
+// NTT line engine with the line length chosen at run time.
+//
+// Same algorithm, butterflies and LDS layout as the compile-time tiles of
+// mw_ntt_tile.h (see the notes there), but log2 of the line length is a
+// run-time value and only the points per lane (2^LOGP) is a template
+// parameter: a round of LOGP stages is one compile-time code path whose
+// shifts and twiddle indices use the run-time stage offset, and the first
+// round, holding the remaining log2(L) mod LOGP stages, has its own path per
+// remainder.  One kernel can then run lines of every length, which the
+// persistent executor needs (jobs of different N in one launch).
+//
+// Workgroups may be wider than a tile (lines * L/P lanes): lanes beyond it are
+// inactive but still reach every barrier.
+#pragma once
+#include "mw_ntt_tile.h"
+
+namespace mw {
+
+template <int LOGP>
+__device__ __forceinline__ u32 rt_pad(u32 j, u32 logl) {
+  return logl > (u32)LOGP ? j + (j >> LOGP) : j;
+}
+
+__device__ __forceinline__ u32 rt_npad(u32 logl, u32 logp) {
+  const u32 L = 1u << logl;
+  return (logl > logp ? L + (L >> logp) : L) + 1;
+}
+
+// One round of NP stages (NP <= LOGP) starting at stage s0 of the line.
+template <int W, int LOGP, int NP, int DIR>
+__device__ __forceinline__ void rt_round(Res<W>* line, bool active, u32 logl, u32 s0, u32 tid, u32 base,
+                                         const Tw<W>* __restrict__ tw, const NttParams<W>& p, bool last_inv,
+                                         bool canon) {
+  constexpr int P = 1 << LOGP;
+  if (active) {
+    const u32 L0 = logl - s0 - LOGP;
+    const u32 base_j = ((tid >> L0) << (L0 + LOGP)) | (tid & ((1u << L0) - 1u));
+    Res<W> x[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) x[u] = line[rt_pad<LOGP>(base_j | ((u32)u << L0), logl)];
+#pragma unroll
+    for (int st0 = 0; st0 < NP; ++st0) {
+      const int st = (DIR == DIR_FWD) ? st0 : (NP - 1 - st0);
+      const u32 s = s0 + st;
+      const int ib = LOGP - 1 - st;
+      const int ngroups = 1 << st;
+#pragma unroll
+      for (int gi = 0; gi < ngroups; ++gi) {
+        const u32 j0 = base_j | ((u32)(gi << (ib + 1)) << L0);
+        const u32 g = j0 >> (logl - s);
+        if (DIR == DIR_INV && s == 0 && last_inv) {
+#pragma unroll
+          for (int lo = 0; lo < (1 << ib); ++lo) {
+            const int u = (gi << (ib + 1)) | lo;
+            gs_bfly_last(x[u], x[u | (1 << ib)], p.ninv, p.ninv_w1, p.M);
+          }
+        } else {
+          const Tw<W> t = load_tw(tw, (base << s) + g);
+#pragma unroll
+          for (int lo = 0; lo < (1 << ib); ++lo) {
+            const int u = (gi << (ib + 1)) | lo;
+            if (DIR == DIR_FWD) ct_bfly(x[u], x[u | (1 << ib)], t, p.M);
+            else gs_bfly(x[u], x[u | (1 << ib)], t, p.M);
+          }
+        }
+      }
+    }
+    if (canon) {
+#pragma unroll
+      for (int u = 0; u < P; ++u) x[u] = canon16(x[u], p.M);
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) line[rt_pad<LOGP>(base_j | ((u32)u << L0), logl)] = x[u];
+  }
+  __syncthreads();
+}
+
+template <int W, int LOGP, int DIR>
+__device__ __forceinline__ void rt_first_round(u32 p0, Res<W>* line, bool active, u32 logl, u32 tid, u32 base,
+                                               const Tw<W>* __restrict__ tw, const NttParams<W>& p,
+                                               bool last_inv, bool canon) {
+  // p0 in [1, LOGP]: stages 0 .. p0-1 of the line
+  if constexpr (LOGP >= 1) {
+    if (p0 == 1) { rt_round<W, LOGP, 1, DIR>(line, active, logl, 0, tid, base, tw, p, last_inv, canon); return; }
+  }
+  if constexpr (LOGP >= 2) {
+    if (p0 == 2) { rt_round<W, LOGP, 2, DIR>(line, active, logl, 0, tid, base, tw, p, last_inv, canon); return; }
+  }
+  if constexpr (LOGP >= 3) {
+    if (p0 == 3) { rt_round<W, LOGP, 3, DIR>(line, active, logl, 0, tid, base, tw, p, last_inv, canon); return; }
+  }
+  if constexpr (LOGP >= 4) {
+    rt_round<W, LOGP, 4, DIR>(line, active, logl, 0, tid, base, tw, p, last_inv, canon);
+  }
+}
+
+// All stages of a line of 2^logl points (logl >= LOGP) held in LDS.
+template <int W, int LOGP, int DIR>
+__device__ __forceinline__ void rt_line_stages(Res<W>* line, bool active, u32 logl, u32 tid, u32 base,
+                                               const Tw<W>* __restrict__ tw, const NttParams<W>& p, bool last_inv,
+                                               bool final_fwd) {
+  const u32 R = (logl + LOGP - 1) / LOGP;
+  const u32 p0 = logl - LOGP * (R - 1);
+  if (DIR == DIR_FWD) {
+    rt_first_round<W, LOGP, DIR>(p0, line, active, logl, tid, base, tw, p, last_inv, final_fwd && R == 1);
+    for (u32 r = 1; r < R; ++r)
+      rt_round<W, LOGP, LOGP, DIR>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p, last_inv,
+                                   final_fwd && r == R - 1);
+  } else {
+    for (u32 r = R - 1; r >= 1; --r)
+      rt_round<W, LOGP, LOGP, DIR>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p, last_inv, false);
+    rt_first_round<W, LOGP, DIR>(p0, line, active, logl, tid, base, tw, p, last_inv, false);
+  }
+}
+
+// One column or row tile of a single transform (batch index 0 of p.src /
+// p.dst), with run-time line length.  `tile` indexes the tiles of the pass.
+template <int W, int LOGP, int DIR, int MODE>
+__device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 tile) {
+  static_assert(MODE == MODE_COL || MODE == MODE_ROW, "two-pass tiles only");
+  const u32 log_n = p.log_n, log_n1 = p.log_n1, log_n2 = log_n - log_n1;
+  const u32 logl = MODE == MODE_COL ? log_n1 : log_n2;
+  const u32 L = 1u << logl;
+  const u32 npad = rt_npad(logl, LOGP);
+  const u32 lines = p.lines;
+  const u32 log_lines = __builtin_ctz(lines);
+  const u32 tpl = L >> LOGP;
+  const u32 T = lines * tpl;
+  const u32 t = threadIdx.x;
+  const bool active = t < T;
+  const u32 line_id = active ? t / tpl : 0;
+  const u32 lane = t % tpl;
+  const u32 nelem = lines << logl;
+  const u32 nthreads = blockDim.x;
+
+  u32 c0 = 0, b_lo = 0;
+  if (MODE == MODE_COL) c0 = tile * lines;
+  else b_lo = tile;
+
+  // ---- device memory -> LDS ----
+  if (MODE == MODE_COL) {
+    const u64 N2 = (u64)1 << log_n2;
+    for (u32 e = t; e < nelem; e += nthreads) {
+      const u32 r = e >> log_lines, c = e & (lines - 1);
+      lds[c * npad + rt_pad<LOGP>(r, logl)] = ResIO<W>::load(p.src + r * N2 + c0 + c);
+    }
+  } else {
+    const u32 n1_over_g = (1u << log_n1) >> log_lines;
+    if (DIR == DIR_INV && p.permute) {
+      const u32 col = brev(b_lo, log_n1 - log_lines) << log_lines;
+      for (u32 e = t; e < nelem; e += nthreads) {
+        const u32 lp = e >> log_lines, jj = e & (lines - 1);
+        lds[brev(jj, log_lines) * npad + rt_pad<LOGP>(brev(lp, logl), logl)] =
+            ResIO<W>::load(p.src + ((u64)lp << log_n1) + col + jj);
+      }
+    } else {
+      for (u32 e = t; e < nelem; e += nthreads) {
+        const u32 j = e >> logl, l = e & (L - 1);
+        const u32 b = j * n1_over_g + b_lo;
+        lds[j * npad + rt_pad<LOGP>(l, logl)] = ResIO<W>::load(p.src + ((u64)b << logl) + l);
+      }
+    }
+  }
+  __syncthreads();
+
+  u32 base = 1;
+  if (MODE == MODE_ROW) base = (1u << log_n1) + line_id * ((1u << log_n1) >> log_lines) + b_lo;
+  const bool last_inv = (DIR == DIR_INV) && (MODE == MODE_COL);
+  const bool final_fwd = (DIR == DIR_FWD) && (MODE == MODE_ROW);
+  rt_line_stages<W, LOGP, DIR>(lds + line_id * npad, active, logl, lane, base, p.tw, p, last_inv, final_fwd);
+
+  // ---- LDS -> device memory ----
+  if (MODE == MODE_COL) {
+    const u64 N2 = (u64)1 << log_n2;
+    for (u32 e = t; e < nelem; e += nthreads) {
+      const u32 r = e >> log_lines, c = e & (lines - 1);
+      ResIO<W>::store(p.dst + r * N2 + c0 + c, lds[c * npad + rt_pad<LOGP>(r, logl)]);
+    }
+  } else {
+    const u32 n1_over_g = (1u << log_n1) >> log_lines;
+    if (DIR == DIR_FWD && p.permute) {
+      const u32 col = brev(b_lo, log_n1 - log_lines) << log_lines;
+      for (u32 e = t; e < nelem; e += nthreads) {
+        const u32 lp = e >> log_lines, jj = e & (lines - 1);
+        ResIO<W>::store(p.dst + ((u64)lp << log_n1) + col + jj,
+                        lds[brev(jj, log_lines) * npad + rt_pad<LOGP>(brev(lp, logl), logl)]);
+      }
+    } else {
+      for (u32 e = t; e < nelem; e += nthreads) {
+        const u32 j = e >> logl, l = e & (L - 1);
+        const u32 b = j * n1_over_g + b_lo;
+        ResIO<W>::store(p.dst + ((u64)b << logl) + l, lds[j * npad + rt_pad<LOGP>(l, logl)]);
+      }
+    }
+  }
+}
+
+// Fused row tile of a negacyclic product: the last log N2 forward stages of
+// a (p.src) and of b (src2) on the same `lines` consecutive rows, their
+// point-wise Barrett product, then the first log N2 inverse stages, written
+// back over a's rows.  Everything stays in bit-reversed order, which is the
+// order the inverse's row pass takes, so no permutation is needed.  `lds`
+// holds 2 * lines * npad residues.  `pi` carries the inverse table and N^-1.
+template <int W, int LOGP>
+__device__ __forceinline__ void rt_fused_row(const NttParams<W>& pf, const NttParams<W>& pi, const Res<W>* src2,
+                                             Res<W>* lds, u32 tile) {
+  const u32 log_n = pf.log_n, log_n1 = pf.log_n1, log_n2 = log_n - log_n1;
+  const u32 logl = log_n2;
+  const u32 L = 1u << logl;
+  const u32 npad = rt_npad(logl, LOGP);
+  const u32 lines = pf.lines;
+  const u32 tpl = L >> LOGP;
+  const u32 T = lines * tpl;
+  const u32 t = threadIdx.x;
+  const bool active = t < T;
+  const u32 line_id = active ? t / tpl : 0;
+  const u32 lane = t % tpl;
+  const u32 nelem = lines << logl;
+  const u32 nthreads = blockDim.x;
+  const u32 row0 = tile * lines;
+  Res<W>* la = lds;
+  Res<W>* lb = lds + lines * npad;
+
+  for (u32 e = t; e < nelem; e += nthreads) {
+    const u32 j = e >> logl, l = e & (L - 1);
+    const u64 off = ((u64)(row0 + j) << logl) + l;
+    la[j * npad + rt_pad<LOGP>(l, logl)] = ResIO<W>::load(pf.src + off);
+    lb[j * npad + rt_pad<LOGP>(l, logl)] = ResIO<W>::load(src2 + off);
+  }
+  __syncthreads();
+  const u32 base = (1u << log_n1) + row0 + line_id;
+  rt_line_stages<W, LOGP, DIR_FWD>(la + line_id * npad, active, logl, lane, base, pf.tw, pf, false, true);
+  rt_line_stages<W, LOGP, DIR_FWD>(lb + line_id * npad, active, logl, lane, base, pf.tw, pf, false, true);
+  for (u32 e = t; e < nelem; e += nthreads) {
+    const u32 j = e >> logl, l = e & (L - 1);
+    const u32 idx = j * npad + rt_pad<LOGP>(l, logl);
+    la[idx] = barrett_mul(la[idx], lb[idx], pf.M);
+  }
+  __syncthreads();
+  rt_line_stages<W, LOGP, DIR_INV>(la + line_id * npad, active, logl, lane, base, pi.tw, pi, false, false);
+  for (u32 e = t; e < nelem; e += nthreads) {
+    const u32 j = e >> logl, l = e & (L - 1);
+    ResIO<W>::store(pf.dst + ((u64)(row0 + j) << logl) + l, la[j * npad + rt_pad<LOGP>(l, logl)]);
+  }
+}
+
+}  // namespace mw

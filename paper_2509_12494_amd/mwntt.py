@@ -22,7 +22,16 @@ MW_OK = 0
 NTT_BITREV_OUT = 0x1
 NTT_BITREV_IN = 0x2
 
+NTT_JOB_FORWARD = 0
+NTT_JOB_INVERSE = 1
+NTT_JOB_POLYMUL = 2
+
 _lib = None
+
+
+class NttJob(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("op", ctypes.c_uint32), ("in_", ctypes.c_void_p),
+                ("in2", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
 class MwError(RuntimeError):
@@ -57,6 +66,11 @@ def lib() -> ctypes.CDLL:
         "ntt_plan_get_tiles": (ctypes.c_int, [vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
         "ntt_forward": (ctypes.c_int, [vp, vp, vp, u32, vp]),
         "ntt_inverse": (ctypes.c_int, [vp, vp, vp, u32, vp]),
+        "ntt_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(NttJob), u32]),
+        "ntt_batch_run": (ctypes.c_int, [vp, vp]),
+        "ntt_batch_info": (ctypes.c_int, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+        "ntt_batch_check": (ctypes.c_int, [vp]),
+        "ntt_batch_destroy": (ctypes.c_int, [vp]),
         "mw_canonical_root": (ctypes.c_int, [u64p, u32, u32, u64p]),
         "mw_shoup_companion": (ctypes.c_int, [u64p, u64p, u32, u64p]),
         "mw_barrett_mu": (ctypes.c_int, [u64p, u32, u64p]),
@@ -221,6 +235,52 @@ class NttPlan:
 
 def ntt_plan(log2n: int, q: int, limbs: int, psi: Optional[int] = None, flags: int = 0) -> NttPlan:
     return NttPlan(log2n, q, limbs, psi, flags)
+
+
+class NttBatch:
+    """Owning wrapper of an ntt_batch_t: many jobs, one launch per phase per run.
+
+    jobs: iterable of (plan, op, inp, inp2, out) with op one of NTT_JOB_*; inp2
+    is None except for NTT_JOB_POLYMUL.  The wrapper keeps references to the
+    plans and buffers so they outlive the batch."""
+
+    def __init__(self, jobs):
+        jobs = list(jobs)
+        arr = (NttJob * len(jobs))()
+        for i, (plan, op, inp, inp2, out) in enumerate(jobs):
+            arr[i].plan = plan._h.value
+            arr[i].op = op
+            arr[i].in_ = _ptr(inp)
+            arr[i].in2 = _ptr(inp2) if inp2 is not None else None
+            arr[i].out = _ptr(out)
+        h = ctypes.c_void_p()
+        _check(lib().ntt_batch_create(ctypes.byref(h), arr, len(jobs)), "ntt_batch_create")
+        self._h = h
+        self._keep = jobs
+
+    def run(self, stream=None) -> None:
+        _check(lib().ntt_batch_run(self._h, _stream(stream)), "ntt_batch_run")
+
+    def check(self) -> None:
+        """Synchronize and raise if a run failed inside the kernel."""
+        _check(lib().ntt_batch_check(self._h), "ntt_batch_check")
+
+    def info(self):
+        t, w = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().ntt_batch_info(self._h, ctypes.byref(t), ctypes.byref(w)), "ntt_batch_info")
+        return {"tiles": t.value, "launches": w.value}
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().ntt_batch_destroy(self._h), "ntt_batch_destroy")
+            self._h = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,191 @@
+"""The batched executor against the oracle, bit for bit.
+
+Mixed lengths and modulus widths in one run (forward, inverse, fused
+products), repeated runs of one batch, hipGraph capture with several replays
+interleaved with eager work, and the paper-scale
+mixed batch (96 polynomials, N = 2^12..2^16, 60/124-bit) and fused products
+(256 pairs at N = 2^14) on sampled outputs."""
+import functools
+
+import pytest
+
+import oracle
+from paper_2509_12494_amd import mwntt
+from paper_2509_12494_amd import workloads as W
+
+from .gpu_util import announce, dev, host_ints, prime, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def _plan(log2n, bits, seed):
+    return mwntt.ntt_plan(log2n, prime(bits, seed), W.limbs_for_bits(bits))
+
+
+def _jobs_small():
+    """Mixed small jobs whose outputs the oracle computes in full."""
+    specs = []
+    for i, (log2n, bits) in enumerate([(6, 60), (6, 124), (7, 124), (8, 60), (9, 124), (10, 60), (10, 124),
+                                       (7, 60), (8, 124)]):
+        specs.append((log2n, bits, 40 + i % 3))
+    return specs
+
+
+def test_mixed_forward_inverse_product_small():
+    require_gpu()
+    import torch
+    jobs, checks = [], []
+    for k, (log2n, bits, seed) in enumerate(_jobs_small()):
+        plan = _plan(log2n, bits, seed)
+        q, limbs, n = plan.q, plan.limbs, plan.n
+        g = W.rng(500 + k)
+        A = W.uniform_residues(g, q, n, limbs)
+        B = W.uniform_residues(g, q, n, limbs)
+        a, b = dev(A), dev(B)
+        op = k % 3
+        out = torch.empty_like(a)
+        a_i, b_i = W.to_ints(A), W.to_ints(B)
+        if op == 0:
+            jobs.append((plan, mwntt.NTT_JOB_FORWARD, a, None, out))
+            checks.append((out, limbs, oracle.ntt.ntt_negacyclic(a_i, q)))
+        elif op == 1:
+            jobs.append((plan, mwntt.NTT_JOB_INVERSE, a, None, out))
+            checks.append((out, limbs, oracle.ntt.intt_negacyclic(a_i, q)))
+        else:
+            jobs.append((plan, mwntt.NTT_JOB_POLYMUL, a, b, out))
+            checks.append((out, limbs, oracle.polymul.negacyclic(a_i, b_i, q)))
+    batch = mwntt.NttBatch(jobs)
+    announce("batch small", batch.info())
+    for rep in range(3):
+        for out, _, _ in checks:
+            out.zero_()
+        batch.run()
+        batch.check()
+        for i, (out, limbs, want) in enumerate(checks):
+            assert host_ints(out, limbs) == want, f"run {rep} job {i}"
+    batch.destroy()
+
+
+def test_graph_capture_replays():
+    require_gpu()
+    import torch
+    plan60, plan124 = _plan(9, 60, 41), _plan(11, 124, 42)
+    A = W.uniform_residues(W.rng(7), plan60.q, plan60.n, 1)
+    B = W.uniform_residues(W.rng(8), plan124.q, plan124.n, 2)
+    C = W.uniform_residues(W.rng(9), plan124.q, plan124.n, 2)
+    a, b, c = dev(A), dev(B), dev(C)
+    oa, ob = torch.empty_like(a), torch.empty_like(b)
+    batch = mwntt.NttBatch([(plan60, mwntt.NTT_JOB_FORWARD, a, None, oa),
+                            (plan124, mwntt.NTT_JOB_POLYMUL, b, c, ob)])
+    want_a = oracle.ntt.ntt_negacyclic(W.to_ints(A), plan60.q)
+    n = plan124.n
+    ks = [0, 1, n // 2, n - 1]
+    want_b = oracle.polymul.negacyclic_at(W.to_ints(B), W.to_ints(C), plan124.q, ks)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        batch.run(stream=s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        oa.zero_()
+        ob.fill_(0)
+        torch.cuda.synchronize()
+        announce("graph replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        assert host_ints(oa, 1) == want_a, rep
+        got = host_ints(ob, 2)
+        assert [got[k] for k in ks] == want_b, rep
+        batch.run()            # eager run between replays
+        batch.check()
+        assert host_ints(oa, 1) == want_a, rep
+    del g
+    batch.destroy()
+
+
+def test_paper_mixed_batch_96():
+    """96 polynomials, N uniform over 2^12..2^16, even index 60-bit, odd 124-bit."""
+    require_gpu()
+    import torch
+    polys = W.config_batched()
+    jobs, plain = [], []
+    plans = {}
+    for i, (log2n, q, limbs, coeffs) in enumerate(polys):
+        plan = plans.setdefault((log2n, q), mwntt.ntt_plan(log2n, q, limbs))
+        x = dev(coeffs)
+        y = torch.empty_like(x)
+        jobs.append((plan, mwntt.NTT_JOB_FORWARD, x, None, y))
+        plain.append((plan, x, y, limbs, q, log2n))
+    batch = mwntt.NttBatch(jobs)
+    announce("batch 96", batch.info())
+    batch.run()
+    batch.check()
+    for i, (plan, x, y, limbs, q, log2n) in enumerate(plain):
+        ref = torch.empty_like(x)
+        plan.forward(ref, x)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, y), f"job {i}"
+        if i % 16 == 0:
+            n = 1 << log2n
+            a = host_ints(x, limbs)
+            got = host_ints(y, limbs)
+            ks = [0, n - 1, (i * 7919) % n]
+            assert [got[k] for k in ks] == oracle.ntt.forward_at(a, q, ks), f"job {i}"
+    # and back: inverse jobs restore every input
+    inv_jobs = [(p, mwntt.NTT_JOB_INVERSE, y, None, y) for (p, x, y, _, _, _) in plain]
+    binv = mwntt.NttBatch(inv_jobs)
+    binv.run()
+    binv.check()
+    for i, (plan, x, y, limbs, q, log2n) in enumerate(plain):
+        assert torch.equal(x, y), f"job {i}"
+    batch.destroy()
+    binv.destroy()
+
+
+def test_paper_fused_products_256():
+    """256 negacyclic products at N = 2^14, 124-bit, sampled against schoolbook."""
+    require_gpu()
+    import torch
+    q, A, B = W.config_fused()
+    pairs, n = A.shape[0], A.shape[1]
+    plan = mwntt.ntt_plan(14, q, 2)
+    a = dev(A.reshape(-1, 2))
+    b = dev(B.reshape(-1, 2))
+    c = torch.empty_like(a)
+    jobs = [(plan, mwntt.NTT_JOB_POLYMUL, a[i * n:(i + 1) * n], b[i * n:(i + 1) * n], c[i * n:(i + 1) * n])
+            for i in range(pairs)]
+    batch = mwntt.NttBatch(jobs)
+    announce("fused 256", batch.info())
+    batch.run()
+    batch.check()
+    for i in (0, 1, 97, 255):
+        ai = W.to_ints(A[i])
+        bi = W.to_ints(B[i])
+        got = host_ints(c[i * n:(i + 1) * n], 2)
+        ks = [0, 1, n // 2, n - 1, (i * 131) % n]
+        assert [got[k] for k in ks] == oracle.polymul.negacyclic_at(ai, bi, q, ks), f"pair {i}"
+    # the whole product of pair 5 equals plain forward / vec_mulmod / inverse
+    fa, fb = torch.empty(n, 2, dtype=torch.int64, device="cuda"), torch.empty(n, 2, dtype=torch.int64, device="cuda")
+    plan.forward(fa, a[5 * n:6 * n])
+    plan.forward(fb, b[5 * n:6 * n])
+    mwntt.vec_mulmod(fa, fa, fb, q, 2)
+    plan.inverse(fb, fa)
+    torch.cuda.synchronize()
+    assert torch.equal(fb, c[5 * n:6 * n])
+    batch.destroy()
+
+
+def test_batch_argument_errors():
+    require_gpu()
+    import torch
+    plan = _plan(5, 124, 42)          # N = 2^5: below the executor's 2^6
+    x = torch.zeros(32, 2, dtype=torch.int64, device="cuda")
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.NttBatch([(plan, mwntt.NTT_JOB_FORWARD, x, None, x)])
+    assert e.value.status == -3
+    p60 = mwntt.ntt_plan(8, (1 << 31) * 0 + prime(60, 41), 1)
+    y = torch.zeros(256, 1, dtype=torch.int64, device="cuda")
+    with pytest.raises(mwntt.MwError):
+        mwntt.NttBatch([(p60, mwntt.NTT_JOB_POLYMUL, y, None, y)])   # product without b
