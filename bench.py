@@ -45,6 +45,36 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def time_calls(fn, stream, reps=20, warm=3):
+    """Mean microseconds per call of fn() on `stream` (HIP events)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def time_graph(fn, stream, reps=20):
+    """Capture fn(stream) into a hipGraph, then mean microseconds per replay."""
+    import torch
+    s = torch.cuda.Stream()
+    fn(s.cuda_stream)            # eager warm-up on the capture stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        fn(s.cuda_stream)
+    torch.cuda.synchronize()
+    us = time_calls(g.replay, torch.cuda.current_stream(), reps=reps)
+    del g
+    return us
+
+
 def cpu_baseline(wl, budget_s=12.0):
     """The oracle (plain Python integers, one core) on a bounded sample of the
     same workload: forward-NTT outputs of the 2^16-point polynomial computed one
@@ -155,18 +185,49 @@ def main():
     B = args.batch
     bpoly = mwntt.to_device(W.uniform_residues(W.rng(2100), q, n * B, limbs))
     bspec = torch.empty_like(bpoly)
-    for _ in range(3):
-        plan.forward(bspec, bpoly, batch=B, stream=sp)
-    torch.cuda.synchronize()
-    reps = 20
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        plan.forward(bspec, bpoly, batch=B, stream=sp)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    batched_us = e0.elapsed_time(e1) * 1e3 / reps
+    batched_us = time_calls(lambda: plan.forward(bspec, bpoly, batch=B, stream=sp), stream)
     batched_ntt_s = B / (batched_us * 1e-6)
+    # the same 96 transforms through the batched executor, replayed from a graph
+    ex = mwntt.NttBatch([(plan, mwntt.NTT_JOB_FORWARD, bpoly[i * n:(i + 1) * n], None, bspec[i * n:(i + 1) * n])
+                         for i in range(B)])
+    exec_us = time_graph(lambda s_: ex.run(stream=s_), stream)
+    legs = {"homogeneous_2e16": {"batch": B, "ntt_forward_us_per_call": round(batched_us, 2),
+                                 "ntt_forward_ntt_s": round(batched_ntt_s, 1),
+                                 "executor_graph_us": round(exec_us, 2),
+                                 "executor_ntt_s": round(B / (exec_us * 1e-6), 1)}}
+    ex.destroy()
+
+    # mixed batch: 96 polynomials, N uniform over 2^12..2^16, 60/124-bit, forward
+    mixed = W.config_batched()
+    mplans, mjobs, mbfly = {}, [], 0
+    for (lg, qm, lm, coeffs) in mixed:
+        pl = mplans.setdefault((lg, qm), mwntt.ntt_plan(lg, qm, lm))
+        x = mwntt.to_device(coeffs)
+        mjobs.append((pl, mwntt.NTT_JOB_FORWARD, x, None, torch.empty_like(x)))
+        mbfly += (1 << (lg - 1)) * lg
+    mb = mwntt.NttBatch(mjobs)
+    mixed_us = time_graph(lambda s_: mb.run(stream=s_), stream)
+    legs["mixed_96"] = {"polys": len(mixed), "us_per_run": round(mixed_us, 2),
+                        "polys_s": round(len(mixed) / (mixed_us * 1e-6), 1),
+                        "gbutterfly_s": round(mbfly / (mixed_us * 1e-6) / 1e9, 2)}
+    mb.destroy()
+
+    # fused products: 256 pairs at N = 2^14, 124-bit
+    qf, FA, FB = W.config_fused()
+    pairs, nf = FA.shape[0], FA.shape[1]
+    fplan = mwntt.ntt_plan(14, qf, 2)
+    fa, fb = mwntt.to_device(FA.reshape(-1, 2)), mwntt.to_device(FB.reshape(-1, 2))
+    fc = torch.empty_like(fa)
+    fbatch = mwntt.NttBatch([(fplan, mwntt.NTT_JOB_POLYMUL, fa[i * nf:(i + 1) * nf], fb[i * nf:(i + 1) * nf],
+                              fc[i * nf:(i + 1) * nf]) for i in range(pairs)])
+    fused_us = time_graph(lambda s_: fbatch.run(stream=s_), stream)
+    legs["fused_256x2e14"] = {"pairs": pairs, "us_per_run": round(fused_us, 2),
+                              "products_s": round(pairs / (fused_us * 1e-6), 1),
+                              "ntt_equiv_s": round(3 * pairs / (fused_us * 1e-6), 1)}
+    fbatch.destroy()
+    fplan.destroy()
+    for pl in mplans.values():
+        pl.destroy()
 
     # roofline of the dominant call: the batched forward transform (two kernels:
     # column pass + row pass), ALU-bound
@@ -197,6 +258,7 @@ def main():
         "batched": {"batch": B, "us_per_call": round(batched_us, 2), "ntt_s": round(batched_ntt_s, 1),
                     "speedup_vs_plain_forward": round(batched_ntt_s / (1e6 / lat["ntt_forward"]["p50_us"]), 2),
                     "gmulmod_s": round(B * bfly / (batched_us * 1e-6) / 1e9, 3)},
+        "legs": legs,
         "roofline": {"bound": "alu", "kernel": "ntt_forward batched (column + row pass kernels)",
                      "achieved": round(achieved_tops, 3), "peak": round(INT32_PEAK_TOPS, 2),
                      "unit": "Tint32op/s", "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": None,

@@ -56,7 +56,8 @@ enum mw_status {
   MW_ESIZE = -3,     /* transform length outside 2^1 .. 2^17 */
   MW_ENOMEM = -4,    /* device or host allocation failed */
   MW_EDEVICE = -5,   /* HIP runtime error (launch failure, no device) */
-  MW_EROOT = -6      /* supplied root is not a primitive 2N-th root */
+  MW_EROOT = -6,     /* supplied root is not a primitive 2N-th root */
+  MW_EBUSY = -7      /* serving: the request has not completed yet */
 };
 
 /* Returns a static string describing a status code. */
@@ -178,6 +179,87 @@ int ntt_batch_check(ntt_batch_t batch);
 int ntt_batch_destroy(ntt_batch_t batch);
 
 /* ------------------------------------------------------------------------ */
+/* Serving runtime: continuous batching of NTT / BLAS requests.              */
+/*                                                                           */
+/* Requests are queued in arrival order.  A scheduler thread admits the     */
+/* oldest requests whose device memory (output + scratch) fits in the       */
+/* remaining HBM budget, forms a batch of up to max_batch of them and        */
+/* launches it on one of max_inflight streams (transform and product        */
+/* requests through the batched executor, BLAS requests as their own        */
+/* kernels), while earlier batches are still running: requests that arrive */
+/* during a batch join the next one as soon as a stream and memory are      */
+/* free, and batches overlap on the device.  Completion is detected from    */
+/* stream events; latency is completion minus submission.  Admission is     */
+/* first-in first-out: a request that does not fit blocks the ones behind   */
+/* it until memory is released.                                             */
+/* ------------------------------------------------------------------------ */
+typedef struct mw_server_s* mw_server_t;
+
+typedef struct {
+  size_t hbm_budget;      /* bytes of device memory for outputs and scratch */
+  uint32_t max_inflight;  /* batches on the device at once (streams), >= 1 */
+  uint32_t max_batch;     /* requests per batch, 1 .. 256 */
+  uint32_t dry_run;       /* 1: scheduler only, no device memory or work; every
+                             request completes after a modelled time and has no
+                             output (for testing admission and queueing) */
+} mw_server_config;
+
+enum mw_request_op {
+  MW_REQ_NTT_FORWARD = 0, MW_REQ_NTT_INVERSE = 1, MW_REQ_POLYMUL = 2,
+  MW_REQ_VEC_ADDMOD = 3, MW_REQ_VEC_SUBMOD = 4, MW_REQ_VEC_MULMOD = 5, MW_REQ_VEC_AXPYMOD = 6
+};
+
+/* One request.  Transform and product requests take q, N and the width from
+ * `plan` (N >= 2^6); BLAS requests take q, limbs, n (and alpha for axpy:
+ * out = alpha*in + in2).  `in` / `in2` are device buffers owned by the
+ * caller that must stay valid until the request completes; in2 is b for
+ * products and BLAS, NULL otherwise. */
+typedef struct {
+  uint32_t op;
+  ntt_plan_t plan;
+  uint64_t q[2];
+  uint32_t limbs;
+  uint64_t alpha[2];
+  uint64_t n;
+  const void* in;
+  const void* in2;
+} mw_request;
+
+typedef struct {
+  uint64_t submitted, completed, batches, max_batch_seen;
+  uint64_t queue_peak;          /* most requests waiting for admission at once */
+  uint64_t inflight_peak;       /* most batches on the device at once */
+  size_t pool_peak;             /* most budget bytes in use at once */
+} mw_server_stats;
+
+/* Creates the server on the current device (allocates the budget as one
+ * pool, the streams and per-stream descriptor buffers; starts the scheduler
+ * thread). */
+int mw_server_create(mw_server_t* server, const mw_server_config* config);
+/* Queues a request; returns its ticket.  MW_ENOMEM if the request alone can
+ * never fit the budget.  Thread-safe. */
+int mw_server_submit(mw_server_t server, const mw_request* request, uint64_t* ticket);
+/* Result of a request: with wait != 0 blocks until it completes.  On MW_OK
+ * *d_out (may be NULL) is the device buffer holding the output (owned by the
+ * server until mw_server_release) and *latency_us (may be NULL) the
+ * submission-to-completion time.  MW_EBUSY if not complete and wait == 0,
+ * MW_EINVAL for an unknown ticket. */
+int mw_server_result(mw_server_t server, uint64_t ticket, int wait, void** d_out, double* latency_us);
+/* Returns a completed request's output memory to the pool. */
+int mw_server_release(mw_server_t server, uint64_t ticket);
+/* Blocks until every queued request has completed. */
+int mw_server_drain(mw_server_t server);
+int mw_server_get_stats(mw_server_t server, mw_server_stats* stats);
+/* Open-loop replay: submits reqs[i] at arrival_us[i] microseconds after the
+ * call starts (a driver thread), releases each result as soon as it
+ * completes, and writes latency_us[i] = completion - scheduled arrival.
+ * *makespan_us = time from the start to the last completion. */
+int mw_server_replay(mw_server_t server, const mw_request* reqs, const double* arrival_us, uint32_t count,
+                     double* latency_us, double* makespan_us);
+/* Stops the scheduler (after draining) and frees everything. */
+int mw_server_destroy(mw_server_t server);
+
+/* ------------------------------------------------------------------------ */
 /* Host-only helpers (no device needed): the plan's own arithmetic, exposed */
 /* for inspection.                                                           */
 /* ------------------------------------------------------------------------ */
@@ -187,6 +269,9 @@ int mw_canonical_root(const uint64_t* q, uint32_t limbs, uint32_t log2n, uint64_
 int mw_shoup_companion(const uint64_t* w, const uint64_t* q, uint32_t limbs, uint64_t* out);
 /* Barrett constant floor(2^(2b) / q), b = bitlen(q) (b+1 bits, limbs words). */
 int mw_barrett_mu(const uint64_t* q, uint32_t limbs, uint64_t* out);
+/* Asynchronous copy of `bytes` between any two HIP-visible buffers on
+ * `stream` (used to read server-owned outputs). */
+int mw_copy(void* dst, const void* src, size_t bytes, void* stream);
 /* Library version string. */
 const char* mw_version(void);
 

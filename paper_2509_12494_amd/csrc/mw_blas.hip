@@ -58,8 +58,8 @@ __global__ __launch_bounds__(256) void blas_kernel(Res<W>* c, const Res<W>* a,
 #pragma unroll
     for (int v = 0; v < VEC; ++v) ResIO<W>::store(c + base + (u64)v * blockDim.x, blas_elem<W, OP>(x[v], y[v], M, s));
   }
-  // ragged tail: residues [nfull*chunk, n), handled by block 0's slot in the
-  // grid-stride order so exactly one block touches each residue
+  // ragged tail: residues [nfull*chunk, n), handled by the one block whose
+  // turn comes next in the grid-stride order
   if (blockIdx.x == (unsigned)(nfull % gridDim.x)) {
     for (u64 i = nfull * chunk + threadIdx.x; i < n; i += blockDim.x) {
       Res<W> x = ResIO<W>::load(a + i), y = ResIO<W>::load(b + i);
@@ -114,6 +114,19 @@ static int blas_dispatch(void* d_c, const void* d_a, const void* d_b, size_t n, 
   }
 }
 
+// Internal entry for the serving runtime: op 0..3 = add, sub, mul, axpy
+// (axpy: c = alpha*a + b, c may differ from b).
+int blas_launch(int op, void* d_c, const void* d_a, const void* d_b, size_t n, const uint64_t* q, uint32_t limbs,
+                const uint64_t* alpha, void* stream) {
+  switch (op) {
+    case OP_ADD: return blas_dispatch<OP_ADD>(d_c, d_a, d_b, n, q, limbs, nullptr, stream);
+    case OP_SUB: return blas_dispatch<OP_SUB>(d_c, d_a, d_b, n, q, limbs, nullptr, stream);
+    case OP_MUL: return blas_dispatch<OP_MUL>(d_c, d_a, d_b, n, q, limbs, nullptr, stream);
+    case OP_AXPY: return blas_dispatch<OP_AXPY>(d_c, d_a, d_b, n, q, limbs, alpha, stream);
+    default: return MW_EINVAL;
+  }
+}
+
 }  // namespace mw
 
 using namespace mw;
@@ -137,4 +150,12 @@ extern "C" int vec_axpymod(void* d_y, const uint64_t* alpha, const void* d_x, si
                            uint32_t limbs, void* stream) {
   // y <- alpha*x + y: the kernel reads (a = x, b = y) and writes c = y
   return blas_dispatch<OP_AXPY>(d_y, d_x, d_y, n, q, limbs, alpha, stream);
+}
+
+extern "C" int mw_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (bytes == 0) return MW_OK;
+  if (!dst || !src) return MW_EINVAL;
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+             ? MW_OK
+             : MW_EDEVICE;
 }

@@ -13,6 +13,7 @@ extern "C" const char* mw_status_str(int status) {
     case MW_ENOMEM: return "out of memory";
     case MW_EDEVICE: return "HIP device error";
     case MW_EROOT: return "not a primitive 2N-th root of unity";
+    case MW_EBUSY: return "request not complete";
     default: return "unknown status";
   }
 }

@@ -26,49 +26,10 @@
 #include <vector>
 
 #include "mw_common.h"
+#include "mw_exec.h"
 #include "mw_ntt_rt.h"
 
-struct ntt_plan_s;  // defined in mw_ntt.hip
-
 namespace mw {
-
-// Accessors into an ntt_plan_s (defined in mw_ntt.hip).
-struct PlanView {
-  uint32_t log2n, limbs, flags;
-  const uint64_t* q;
-  const void* tw_fwd;
-  const void* tw_inv;
-};
-bool plan_view(const ntt_plan_s* P, PlanView& v, Modulus<4>& m4, Tw<4>& n4, Tw<4>& l4, Modulus<2>& m2, Tw<2>& n2,
-               Tw<2>& l2);
-
-enum { JOB_FWD = 0, JOB_INV = 1, JOB_MUL = 2 };
-constexpr int kExecThreads = 256;
-constexpr int kLogP4 = 2;   // points per lane, two-word moduli
-constexpr int kLogP2 = 3;   // one-word moduli
-
-struct JobDesc {
-  u64 in, in2, out, scratch;
-  u64 tw_fwd, tw_inv;
-  u32 op, limbs, log_n, log_n1;
-  u32 perm_out, perm_in;
-  u32 lines_col, lines_row;
-  u32 tiles[3];
-  u32 nphases;
-};
-
-template <int W>
-struct ModConst {
-  Modulus<W> M;
-  Tw<W> ninv, last;
-};
-
-struct ExecParams {
-  const JobDesc* jobs;
-  const uint2* items;      // this launch's tiles: {job, phase << 16 | tile}
-  const ModConst<4>* mods4;
-  const ModConst<2>* mods2;
-};
 
 template <int W, int LOGP>
 __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J, u32 job, u32 phase, u32 tile,
@@ -139,71 +100,31 @@ __global__ __launch_bounds__(kExecThreads) void exec_kernel(ExecParams ep) {
   else run_item<2, kLogP2>(ep, J, job, phase, tile, mw_exec_smem);
 }
 
-}  // namespace mw
-
-using namespace mw;
-
-struct ntt_batch_s {
-  int device = 0;
-  JobDesc* d_jobs = nullptr;
-  uint2* d_items = nullptr;
-  ModConst<4>* d_m4 = nullptr;
-  ModConst<2>* d_m2 = nullptr;
-  void* d_scratch = nullptr;
-  u32 njobs = 0, total = 0;
-  u32 nphases = 0;
-  u32 phase_begin[4] = {0, 0, 0, 0};   // tile ranges of each launch in d_items
-  size_t phase_lds[3] = {0, 0, 0};
-};
-
-namespace {
-
-void free_batch(ntt_batch_s* B) {
-  if (!B) return;
-  if (B->d_jobs) (void)hipFree(B->d_jobs);
-  if (B->d_items) (void)hipFree(B->d_items);
-  if (B->d_m4) (void)hipFree(B->d_m4);
-  if (B->d_m2) (void)hipFree(B->d_m2);
-  if (B->d_scratch) (void)hipFree(B->d_scratch);
-  delete B;
-}
-
-size_t npad_of(u32 logl, u32 logp) {
+static size_t npad_of(u32 logl, u32 logp) {
   const size_t L = (size_t)1 << logl;
   return (logl > logp ? L + (L >> logp) : L) + 1;
 }
 
-template <typename T>
-int upload(T** dst, const std::vector<T>& v) {
-  if (v.empty()) return MW_OK;
-  if (hipMalloc(dst, sizeof(T) * v.size()) != hipSuccess) return MW_ENOMEM;
-  if (hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return MW_EDEVICE;
-  return MW_OK;
-}
-
-}  // namespace
-
-extern "C" int ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t count) {
-  if (!out) return MW_EINVAL;
-  *out = nullptr;
+int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
   if (!jobs || count == 0 || count > 65535) return MW_EINVAL;
-  std::vector<JobDesc> J(count);
-  std::vector<ModConst<4>> m4(count);
-  std::vector<ModConst<2>> m2(count);
-  std::vector<size_t> scr_off(count);
-  size_t scratch_bytes = 0;
-  size_t phase_lds[3] = {0, 0, 0};
+  out = ExecPlan();
+  out.jobs.resize(count);
+  out.m4.resize(count);
+  out.m2.resize(count);
+  out.scratch_bytes.resize(count);
   for (uint32_t i = 0; i < count; ++i) {
     const ntt_job& jb = jobs[i];
     if (!jb.plan || !jb.in || !jb.out || jb.op > NTT_JOB_POLYMUL) return MW_EINVAL;
     if (jb.op == NTT_JOB_POLYMUL && !jb.in2) return MW_EINVAL;
     PlanView v;
-    ModConst<4> c4 = {};
-    ModConst<2> c2 = {};
+    ModConst<4>& c4 = out.m4[i];
+    ModConst<2>& c2 = out.m2[i];
+    c4 = {};
+    c2 = {};
     if (!plan_view(jb.plan, v, c4.M, c4.ninv, c4.last, c2.M, c2.ninv, c2.last)) return MW_EINVAL;
     if (v.log2n < 6) return MW_ESIZE;   // two-pass tiles need N1, N2 >= 8
     if (jb.op == NTT_JOB_POLYMUL && check_modulus(v.q, v.limbs, true) != MW_OK) return MW_EMODULUS;
-    JobDesc& d = J[i];
+    JobDesc& d = out.jobs[i];
     d = {};
     d.in = (u64)jb.in;
     d.in2 = (u64)jb.in2;
@@ -223,92 +144,148 @@ extern "C" int ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t 
     d.lines_row = std::min<u32>(kExecThreads / tpl_r, 1u << l1);
     const u32 ncol = (1u << l2) / d.lines_col, nrow = (1u << l1) / d.lines_row;
     const size_t rsz = 8 * (size_t)v.limbs;
-    size_t lds_c = d.lines_col * npad_of(l1, logp) * rsz, lds_r = d.lines_row * npad_of(l2, logp) * rsz;
+    const size_t lds_c = d.lines_col * npad_of(l1, logp) * rsz, lds_r = d.lines_row * npad_of(l2, logp) * rsz;
+    size_t* pl = out.phase_lds;
     if (d.op == JOB_FWD) {
       d.nphases = 2; d.tiles[0] = ncol; d.tiles[1] = nrow;
-      phase_lds[0] = std::max(phase_lds[0], lds_c);
-      phase_lds[1] = std::max(phase_lds[1], lds_r);
+      pl[0] = std::max(pl[0], lds_c);
+      pl[1] = std::max(pl[1], lds_r);
     } else if (d.op == JOB_INV) {
       d.nphases = 2; d.tiles[0] = nrow; d.tiles[1] = ncol;
-      phase_lds[0] = std::max(phase_lds[0], lds_r);
-      phase_lds[1] = std::max(phase_lds[1], lds_c);
+      pl[0] = std::max(pl[0], lds_r);
+      pl[1] = std::max(pl[1], lds_c);
     } else {
       d.nphases = 3; d.tiles[0] = 2 * ncol; d.tiles[1] = nrow; d.tiles[2] = ncol;
-      phase_lds[0] = std::max(phase_lds[0], lds_c);
-      phase_lds[1] = std::max(phase_lds[1], 2 * lds_r);   // rows of a and b
-      phase_lds[2] = std::max(phase_lds[2], lds_c);
+      pl[0] = std::max(pl[0], lds_c);
+      pl[1] = std::max(pl[1], 2 * lds_r);   // rows of a and b
+      pl[2] = std::max(pl[2], lds_c);
     }
-    scr_off[i] = scratch_bytes;
-    scratch_bytes += (d.op == JOB_MUL ? 2 : 1) * (rsz << v.log2n);
-    scratch_bytes = (scratch_bytes + 255) & ~(size_t)255;
-    m4[i] = c4;
-    m2[i] = c2;
+    out.scratch_bytes[i] = (d.op == JOB_MUL ? 2 : 1) * (rsz << v.log2n);
   }
-  for (size_t l : phase_lds)
+  for (size_t l : out.phase_lds)
     if (l > 160 * 1024) return MW_ESIZE;
   // tiles, phase-major: launch k covers [phase_begin[k], phase_begin[k+1])
-  std::vector<uint2> items;
-  u32 phase_begin[4] = {0, 0, 0, 0};
-  u32 nphases = 0;
   for (u32 ph = 0; ph < 3; ++ph) {
-    phase_begin[ph] = (u32)items.size();
+    out.phase_begin[ph] = (u32)out.items.size();
     for (uint32_t i = 0; i < count; ++i)
-      if (ph < J[i].nphases)
-        for (u32 t = 0; t < J[i].tiles[ph]; ++t) items.push_back(make_uint2(i, (ph << 16) | t));
-    if (items.size() > phase_begin[ph]) nphases = ph + 1;
+      if (ph < out.jobs[i].nphases)
+        for (u32 t = 0; t < out.jobs[i].tiles[ph]; ++t) out.items.push_back(make_uint2(i, (ph << 16) | t));
+    if (out.items.size() > out.phase_begin[ph]) out.nphases = ph + 1;
   }
-  phase_begin[3] = (u32)items.size();
+  out.phase_begin[3] = (u32)out.items.size();
+  return MW_OK;
+}
 
+hipError_t exec_prepare(size_t max_lds) {
+  if (max_lds <= 65536) return hipSuccess;
+  static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(exec_kernel),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  return e;
+}
+
+hipError_t exec_launch(const JobDesc* d_jobs, const uint2* d_items, const ModConst<4>* d_m4,
+                       const ModConst<2>* d_m2, const ExecPlan& plan, hipStream_t s) {
+  ExecParams ep;
+  ep.jobs = d_jobs;
+  ep.mods4 = d_m4;
+  ep.mods2 = d_m2;
+  for (u32 k = 0; k < plan.nphases; ++k) {
+    const u32 n = plan.phase_begin[k + 1] - plan.phase_begin[k];
+    if (n == 0) continue;
+    ep.items = d_items + plan.phase_begin[k];
+    hipLaunchKernelGGL(exec_kernel, dim3(n), dim3(kExecThreads), plan.phase_lds[k], s, ep);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace mw
+
+using namespace mw;
+
+struct ntt_batch_s {
+  int device = 0;
+  ExecPlan plan;
+  JobDesc* d_jobs = nullptr;
+  uint2* d_items = nullptr;
+  ModConst<4>* d_m4 = nullptr;
+  ModConst<2>* d_m2 = nullptr;
+  void* d_scratch = nullptr;
+};
+
+namespace {
+
+void free_batch(ntt_batch_s* B) {
+  if (!B) return;
+  if (B->d_jobs) (void)hipFree(B->d_jobs);
+  if (B->d_items) (void)hipFree(B->d_items);
+  if (B->d_m4) (void)hipFree(B->d_m4);
+  if (B->d_m2) (void)hipFree(B->d_m2);
+  if (B->d_scratch) (void)hipFree(B->d_scratch);
+  delete B;
+}
+
+template <typename T>
+int upload(T** dst, const std::vector<T>& v) {
+  if (v.empty()) return MW_OK;
+  if (hipMalloc(dst, sizeof(T) * v.size()) != hipSuccess) return MW_ENOMEM;
+  if (hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess) return MW_EDEVICE;
+  return MW_OK;
+}
+
+}  // namespace
+
+extern "C" int ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t count) {
+  if (!out) return MW_EINVAL;
+  *out = nullptr;
   ntt_batch_s* B = new (std::nothrow) ntt_batch_s();
   if (!B) return MW_ENOMEM;
-  if (hipGetDevice(&B->device) != hipSuccess) { delete B; return MW_EDEVICE; }
-  int st = MW_OK;
-  if (hipMalloc(&B->d_scratch, scratch_bytes) != hipSuccess) st = MW_ENOMEM;
+  int st = exec_build(jobs, count, B->plan);
+  if (st != MW_OK) {
+    delete B;
+    return st;
+  }
+  if (hipGetDevice(&B->device) != hipSuccess) {
+    delete B;
+    return MW_EDEVICE;
+  }
+  // one scratch allocation, 256-byte aligned slices
+  size_t total = 0;
+  std::vector<size_t> off(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    off[i] = total;
+    total += (B->plan.scratch_bytes[i] + 255) & ~(size_t)255;
+  }
+  if (hipMalloc(&B->d_scratch, total) != hipSuccess) st = MW_ENOMEM;
   if (st == MW_OK)
-    for (uint32_t i = 0; i < count; ++i) J[i].scratch = (u64)((char*)B->d_scratch + scr_off[i]);
-  if (st == MW_OK) st = upload(&B->d_jobs, J);
-  if (st == MW_OK) st = upload(&B->d_items, items);
-  if (st == MW_OK) st = upload(&B->d_m4, m4);
-  if (st == MW_OK) st = upload(&B->d_m2, m2);
-  const size_t max_lds = std::max(phase_lds[0], std::max(phase_lds[1], phase_lds[2]));
-  if (st == MW_OK && max_lds > 65536 &&
-      hipFuncSetAttribute(reinterpret_cast<const void*>(exec_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          160 * 1024) != hipSuccess)
-    st = MW_EDEVICE;
+    for (uint32_t i = 0; i < count; ++i) B->plan.jobs[i].scratch = (u64)((char*)B->d_scratch + off[i]);
+  if (st == MW_OK) st = upload(&B->d_jobs, B->plan.jobs);
+  if (st == MW_OK) st = upload(&B->d_items, B->plan.items);
+  if (st == MW_OK) st = upload(&B->d_m4, B->plan.m4);
+  if (st == MW_OK) st = upload(&B->d_m2, B->plan.m2);
+  const size_t max_lds = std::max(B->plan.phase_lds[0], std::max(B->plan.phase_lds[1], B->plan.phase_lds[2]));
+  if (st == MW_OK && exec_prepare(max_lds) != hipSuccess) st = MW_EDEVICE;
   if (st != MW_OK) {
     free_batch(B);
     return st;
   }
-  B->total = (u32)items.size();
-  B->njobs = count;
-  B->nphases = nphases;
-  for (int k = 0; k < 4; ++k) B->phase_begin[k] = phase_begin[k];
-  for (int k = 0; k < 3; ++k) B->phase_lds[k] = phase_lds[k];
   *out = B;
   return MW_OK;
 }
 
 extern "C" int ntt_batch_run(ntt_batch_t batch, void* stream) {
   if (!batch) return MW_EINVAL;
-  ExecParams ep;
-  ep.jobs = batch->d_jobs;
-  ep.mods4 = batch->d_m4;
-  ep.mods2 = batch->d_m2;
-  for (u32 k = 0; k < batch->nphases; ++k) {
-    const u32 n = batch->phase_begin[k + 1] - batch->phase_begin[k];
-    if (n == 0) continue;
-    ep.items = batch->d_items + batch->phase_begin[k];
-    hipLaunchKernelGGL(exec_kernel, dim3(n), dim3(kExecThreads), batch->phase_lds[k],
-                       reinterpret_cast<hipStream_t>(stream), ep);
-    if (hipGetLastError() != hipSuccess) return MW_EDEVICE;
-  }
-  return MW_OK;
+  return exec_launch(batch->d_jobs, batch->d_items, batch->d_m4, batch->d_m2, batch->plan,
+                     reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+             ? MW_OK
+             : MW_EDEVICE;
 }
 
 extern "C" int ntt_batch_info(ntt_batch_t batch, uint32_t* tiles, uint32_t* launches) {
   if (!batch) return MW_EINVAL;
-  if (tiles) *tiles = batch->total;
-  if (launches) *launches = batch->nphases;
+  if (tiles) *tiles = (uint32_t)batch->plan.items.size();
+  if (launches) *launches = batch->plan.nphases;
   return MW_OK;
 }
 

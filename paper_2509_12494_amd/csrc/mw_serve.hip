@@ -1,0 +1,551 @@
+// Serving runtime: continuous batching of NTT / modular BLAS requests with
+// HBM-budget admission (see the mw_server_* section of mwntt.h).
+//
+// State: a FIFO of queued requests, a first-fit pool over one device
+// allocation of `hbm_budget` bytes (outputs and scratch of admitted
+// requests), and `max_inflight` slots, each a stream with an event and
+// preallocated descriptor buffers (device + pinned host staging).  A
+// scheduler thread loops: it retires slots whose event completed (their
+// requests become complete and their scratch returns to the pool), then, while
+// a slot is free, admits requests from the head of the queue as long as their
+// memory fits and the batch has room, uploads the batch's descriptors with
+// asynchronous copies and launches it (transform / product requests through
+// the batched executor, BLAS requests as their own kernels) on the slot's
+// stream.  Requests arriving meanwhile wait in the queue and go into the next
+// batch on the next free slot, so batches overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mw_common.h"
+#include "mw_exec.h"
+
+namespace mw {
+int blas_launch(int op, void* d_c, const void* d_a, const void* d_b, size_t n, const uint64_t* q, uint32_t limbs,
+                const uint64_t* alpha, void* stream);
+}
+
+using namespace mw;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr uint32_t kMaxBatch = 256;
+constexpr uint32_t kMaxTilesPerJob = 2048;
+
+double now_us() {
+  using namespace std::chrono;
+  return duration<double, std::micro>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t round_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// First-fit allocator over [0, size) with coalescing of free neighbours.
+class Pool {
+ public:
+  void init(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+    size_ = size;
+    used_ = peak_ = 0;
+  }
+  // returns false if no free block is large enough
+  bool alloc(size_t bytes, size_t* off) {
+    if (bytes == 0) {
+      *off = 0;
+      return true;
+    }
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += bytes;
+        peak_ = std::max(peak_, used_);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    if (bytes == 0) return;
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    size_t start = off, len = bytes;
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        start = prev->first;
+        len += prev->second;
+        free_.erase(prev);
+      }
+    }
+    if (next != free_.end() && off + bytes == next->first) {
+      len += next->second;
+      free_.erase(next);
+    }
+    free_[start] = len;
+  }
+  size_t used() const { return used_; }
+  size_t peak() const { return peak_; }
+  size_t size() const { return size_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t size_ = 0, used_ = 0, peak_ = 0;
+};
+
+enum ReqState { RQ_QUEUED, RQ_RUNNING, RQ_DONE, RQ_FAILED };
+
+struct Req {
+  mw_request r;
+  size_t out_bytes = 0, scratch_bytes = 0;
+  size_t out_off = 0, scratch_off = 0;
+  double t_submit = 0, t_done = 0;
+  double cost_us = 0;   // dry-run model
+  ReqState state = RQ_QUEUED;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  JobDesc* d_jobs = nullptr;
+  uint2* d_items = nullptr;
+  ModConst<4>* d_m4 = nullptr;
+  ModConst<2>* d_m2 = nullptr;
+  JobDesc* h_jobs = nullptr;     // pinned staging
+  uint2* h_items = nullptr;
+  ModConst<4>* h_m4 = nullptr;
+  ModConst<2>* h_m2 = nullptr;
+  bool busy = false;
+  double t_end = 0;              // dry run
+  std::vector<uint64_t> tickets;
+};
+
+bool is_ntt(uint32_t op) { return op <= MW_REQ_POLYMUL; }
+
+}  // namespace
+
+struct mw_server_s {
+  mw_server_config cfg{};
+  int device = 0;
+  void* pool_base = nullptr;
+  Pool pool;
+  std::vector<Slot> slots;
+  std::unordered_map<uint64_t, Req> reqs;
+  std::deque<uint64_t> queue;
+  uint64_t next_ticket = 1;
+  uint32_t inflight = 0;
+  mw_server_stats stats{};
+  bool stop = false;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread sched;
+};
+
+namespace {
+
+void* pool_ptr(mw_server_s* S, size_t off) { return S->pool_base ? (char*)S->pool_base + off : nullptr; }
+
+// Launch one batch on a slot (called with the lock held).
+bool launch_batch(mw_server_s* S, Slot& slot, const std::vector<uint64_t>& batch) {
+  slot.tickets = batch;
+  if (S->cfg.dry_run) {
+    double cost = 5.0;
+    for (uint64_t t : batch) cost += S->reqs[t].cost_us;
+    slot.t_end = now_us() + cost;
+    return true;
+  }
+  std::vector<ntt_job> jobs;
+  std::vector<uint64_t> job_tickets;
+  for (uint64_t t : batch) {
+    Req& R = S->reqs[t];
+    if (!is_ntt(R.r.op)) continue;
+    ntt_job j;
+    j.plan = R.r.plan;
+    j.op = R.r.op == MW_REQ_NTT_FORWARD ? NTT_JOB_FORWARD
+                                        : (R.r.op == MW_REQ_NTT_INVERSE ? NTT_JOB_INVERSE : NTT_JOB_POLYMUL);
+    j.in = R.r.in;
+    j.in2 = R.r.op == MW_REQ_POLYMUL ? R.r.in2 : nullptr;
+    j.out = pool_ptr(S, R.out_off);
+    jobs.push_back(j);
+    job_tickets.push_back(t);
+  }
+  if (!jobs.empty()) {
+    ExecPlan plan;
+    if (exec_build(jobs.data(), (uint32_t)jobs.size(), plan) != MW_OK) return false;
+    if (plan.items.size() > (size_t)S->cfg.max_batch * kMaxTilesPerJob) return false;
+    for (size_t i = 0; i < jobs.size(); ++i) plan.jobs[i].scratch = (u64)pool_ptr(S, S->reqs[job_tickets[i]].scratch_off);
+    const size_t nj = plan.jobs.size(), ni = plan.items.size();
+    std::memcpy(slot.h_jobs, plan.jobs.data(), sizeof(JobDesc) * nj);
+    std::memcpy(slot.h_items, plan.items.data(), sizeof(uint2) * ni);
+    std::memcpy(slot.h_m4, plan.m4.data(), sizeof(ModConst<4>) * nj);
+    std::memcpy(slot.h_m2, plan.m2.data(), sizeof(ModConst<2>) * nj);
+    if (hipMemcpyAsync(slot.d_jobs, slot.h_jobs, sizeof(JobDesc) * nj, hipMemcpyHostToDevice, slot.stream) != hipSuccess ||
+        hipMemcpyAsync(slot.d_items, slot.h_items, sizeof(uint2) * ni, hipMemcpyHostToDevice, slot.stream) != hipSuccess ||
+        hipMemcpyAsync(slot.d_m4, slot.h_m4, sizeof(ModConst<4>) * nj, hipMemcpyHostToDevice, slot.stream) != hipSuccess ||
+        hipMemcpyAsync(slot.d_m2, slot.h_m2, sizeof(ModConst<2>) * nj, hipMemcpyHostToDevice, slot.stream) != hipSuccess)
+      return false;
+    const size_t max_lds = std::max(plan.phase_lds[0], std::max(plan.phase_lds[1], plan.phase_lds[2]));
+    if (exec_prepare(max_lds) != hipSuccess) return false;
+    if (exec_launch(slot.d_jobs, slot.d_items, slot.d_m4, slot.d_m2, plan, slot.stream) != hipSuccess) return false;
+  }
+  for (uint64_t t : batch) {
+    Req& R = S->reqs[t];
+    if (is_ntt(R.r.op)) continue;
+    const int op = R.r.op == MW_REQ_VEC_ADDMOD ? 0 : R.r.op == MW_REQ_VEC_SUBMOD ? 1 : R.r.op == MW_REQ_VEC_MULMOD ? 2 : 3;
+    if (blas_launch(op, pool_ptr(S, R.out_off), R.r.in, R.r.in2, R.r.n, R.r.q, R.r.limbs, R.r.alpha, slot.stream) !=
+        MW_OK)
+      return false;
+  }
+  return hipEventRecord(slot.done, slot.stream) == hipSuccess;
+}
+
+void scheduler(mw_server_s* S) {
+  if (!S->cfg.dry_run) (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    bool progress = false;
+    // retire finished batches
+    for (Slot& slot : S->slots) {
+      if (!slot.busy) continue;
+      bool done, failed = false;
+      if (S->cfg.dry_run) {
+        done = now_us() >= slot.t_end;
+      } else {
+        const hipError_t e = hipEventQuery(slot.done);
+        done = e != hipErrorNotReady;
+        failed = done && e != hipSuccess;
+      }
+      if (!done) continue;
+      const double t = now_us();
+      for (uint64_t tk : slot.tickets) {
+        Req& R = S->reqs[tk];
+        R.state = failed ? RQ_FAILED : RQ_DONE;
+        R.t_done = t;
+        S->pool.release(R.scratch_off, R.scratch_bytes);
+        R.scratch_bytes = 0;
+        ++S->stats.completed;
+      }
+      slot.tickets.clear();
+      slot.busy = false;
+      --S->inflight;
+      progress = true;
+    }
+    if (progress) S->cv_done.notify_all();
+    // admit and launch
+    while (S->inflight < S->cfg.max_inflight && !S->queue.empty()) {
+      Slot* slot = nullptr;
+      for (Slot& s : S->slots)
+        if (!s.busy) {
+          slot = &s;
+          break;
+        }
+      if (!slot) break;
+      std::vector<uint64_t> batch;
+      while (!S->queue.empty() && batch.size() < S->cfg.max_batch) {
+        Req& R = S->reqs[S->queue.front()];
+        size_t oo = 0, so = 0;
+        if (!S->pool.alloc(R.out_bytes, &oo)) break;
+        if (!S->pool.alloc(R.scratch_bytes, &so)) {
+          S->pool.release(oo, R.out_bytes);
+          break;
+        }
+        R.out_off = oo;
+        R.scratch_off = so;
+        R.state = RQ_RUNNING;
+        batch.push_back(S->queue.front());
+        S->queue.pop_front();
+      }
+      if (batch.empty()) break;   // the oldest request waits for memory
+      slot->busy = true;
+      ++S->inflight;
+      ++S->stats.batches;
+      S->stats.max_batch_seen = std::max<uint64_t>(S->stats.max_batch_seen, batch.size());
+      S->stats.inflight_peak = std::max<uint64_t>(S->stats.inflight_peak, S->inflight);
+      S->stats.pool_peak = std::max(S->stats.pool_peak, S->pool.used());
+      if (!launch_batch(S, *slot, batch)) {
+        // the batch could not be launched: fail its requests, free the slot
+        for (uint64_t tk : batch) {
+          Req& R = S->reqs[tk];
+          R.state = RQ_FAILED;
+          R.t_done = now_us();
+          S->pool.release(R.scratch_off, R.scratch_bytes);
+          R.scratch_bytes = 0;
+          ++S->stats.completed;
+        }
+        slot->tickets.clear();
+        slot->busy = false;
+        --S->inflight;
+        S->cv_done.notify_all();
+      }
+      progress = true;
+    }
+    if (S->stop && S->queue.empty() && S->inflight == 0) break;
+    if (!progress) {
+      // poll completions often while batches run, otherwise sleep until work
+      if (S->inflight) S->cv_work.wait_for(lk, std::chrono::microseconds(4));
+      else S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+    }
+  }
+}
+
+int validate(mw_server_s* S, const mw_request& r, Req& R) {
+  const uint32_t op = r.op;
+  if (op > MW_REQ_VEC_AXPYMOD || !r.in) return MW_EINVAL;
+  if (is_ntt(op)) {
+    if (!r.plan) return MW_EINVAL;
+    PlanView v;
+    Modulus<4> m4;
+    Tw<4> a4, b4;
+    Modulus<2> m2;
+    Tw<2> a2, b2;
+    if (!plan_view(r.plan, v, m4, a4, b4, m2, a2, b2)) return MW_EINVAL;
+    if (v.log2n < 6) return MW_ESIZE;
+    if (op == MW_REQ_POLYMUL) {
+      if (!r.in2) return MW_EINVAL;
+      if (check_modulus(v.q, v.limbs, true) != MW_OK) return MW_EMODULUS;
+    }
+    const size_t bytes = (size_t)8 * v.limbs << v.log2n;
+    R.out_bytes = round_up(bytes);
+    R.scratch_bytes = round_up((op == MW_REQ_POLYMUL ? 2 : 1) * bytes);
+    R.cost_us = 1.0 + (double)bytes * v.log2n / 8.0e4;
+  } else {
+    if (!r.in2 || r.n == 0) return MW_EINVAL;
+    int st = check_modulus(r.q, r.limbs, op == MW_REQ_VEC_MULMOD);
+    if (st != MW_OK) return st;
+    if (op == MW_REQ_VEC_AXPYMOD) {
+      mwhost::u128 Q = mwhost::from_words(r.q, r.limbs), A = mwhost::from_words(r.alpha, r.limbs);
+      if (A >= Q) return MW_EINVAL;
+    }
+    R.out_bytes = round_up((size_t)8 * r.limbs * r.n);
+    R.scratch_bytes = 0;
+    R.cost_us = 1.0 + (double)R.out_bytes / 4.0e4;
+  }
+  if (R.out_bytes + R.scratch_bytes > S->pool.size()) return MW_ENOMEM;
+  return MW_OK;
+}
+
+void free_server(mw_server_s* S) {
+  for (Slot& s : S->slots) {
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.d_jobs) (void)hipFree(s.d_jobs);
+    if (s.d_items) (void)hipFree(s.d_items);
+    if (s.d_m4) (void)hipFree(s.d_m4);
+    if (s.d_m2) (void)hipFree(s.d_m2);
+    if (s.h_jobs) (void)hipHostFree(s.h_jobs);
+    if (s.h_items) (void)hipHostFree(s.h_items);
+    if (s.h_m4) (void)hipHostFree(s.h_m4);
+    if (s.h_m2) (void)hipHostFree(s.h_m2);
+  }
+  if (S->pool_base) (void)hipFree(S->pool_base);
+  delete S;
+}
+
+}  // namespace
+
+extern "C" int mw_server_create(mw_server_t* out, const mw_server_config* cfg) {
+  if (!out || !cfg) return MW_EINVAL;
+  *out = nullptr;
+  if (cfg->max_inflight < 1 || cfg->max_inflight > 16 || cfg->max_batch < 1 || cfg->max_batch > kMaxBatch ||
+      cfg->hbm_budget < kAlign)
+    return MW_EINVAL;
+  mw_server_s* S = new (std::nothrow) mw_server_s();
+  if (!S) return MW_ENOMEM;
+  S->cfg = *cfg;
+  S->pool.init(cfg->hbm_budget & ~(kAlign - 1));
+  S->slots.resize(cfg->max_inflight);
+  if (!cfg->dry_run) {
+    int st = MW_OK;
+    if (hipGetDevice(&S->device) != hipSuccess) st = MW_EDEVICE;
+    if (st == MW_OK && hipMalloc(&S->pool_base, S->pool.size()) != hipSuccess) st = MW_ENOMEM;
+    const size_t nj = cfg->max_batch, ni = (size_t)cfg->max_batch * kMaxTilesPerJob;
+    for (Slot& s : S->slots) {
+      if (st != MW_OK) break;
+      if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+        st = MW_EDEVICE;
+        break;
+      }
+      if (hipMalloc(&s.d_jobs, sizeof(JobDesc) * nj) != hipSuccess ||
+          hipMalloc(&s.d_items, sizeof(uint2) * ni) != hipSuccess ||
+          hipMalloc(&s.d_m4, sizeof(ModConst<4>) * nj) != hipSuccess ||
+          hipMalloc(&s.d_m2, sizeof(ModConst<2>) * nj) != hipSuccess ||
+          hipHostMalloc(&s.h_jobs, sizeof(JobDesc) * nj) != hipSuccess ||
+          hipHostMalloc(&s.h_items, sizeof(uint2) * ni) != hipSuccess ||
+          hipHostMalloc(&s.h_m4, sizeof(ModConst<4>) * nj) != hipSuccess ||
+          hipHostMalloc(&s.h_m2, sizeof(ModConst<2>) * nj) != hipSuccess)
+        st = MW_ENOMEM;
+    }
+    if (st != MW_OK) {
+      free_server(S);
+      return st;
+    }
+  }
+  try {
+    S->sched = std::thread(scheduler, S);
+  } catch (...) {
+    free_server(S);
+    return MW_ENOMEM;
+  }
+  *out = S;
+  return MW_OK;
+}
+
+extern "C" int mw_server_submit(mw_server_t S, const mw_request* request, uint64_t* ticket) {
+  if (!S || !request || !ticket) return MW_EINVAL;
+  Req R;
+  R.r = *request;
+  std::lock_guard<std::mutex> lk(S->mu);
+  int st = validate(S, *request, R);
+  if (st != MW_OK) return st;
+  R.t_submit = now_us();
+  const uint64_t t = S->next_ticket++;
+  S->reqs.emplace(t, R);
+  S->queue.push_back(t);
+  ++S->stats.submitted;
+  S->stats.queue_peak = std::max<uint64_t>(S->stats.queue_peak, S->queue.size());
+  *ticket = t;
+  S->cv_work.notify_one();
+  return MW_OK;
+}
+
+extern "C" int mw_server_result(mw_server_t S, uint64_t ticket, int wait, void** d_out, double* latency_us) {
+  if (!S) return MW_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return MW_EINVAL;
+  if (wait) {
+    S->cv_done.wait(lk, [&] {
+      const ReqState s = S->reqs[ticket].state;
+      return s == RQ_DONE || s == RQ_FAILED;
+    });
+  }
+  Req& R = S->reqs[ticket];
+  if (R.state == RQ_QUEUED || R.state == RQ_RUNNING) return MW_EBUSY;
+  if (R.state == RQ_FAILED) return MW_EDEVICE;
+  if (d_out) *d_out = pool_ptr(S, R.out_off);
+  if (latency_us) *latency_us = R.t_done - R.t_submit;
+  return MW_OK;
+}
+
+extern "C" int mw_server_release(mw_server_t S, uint64_t ticket) {
+  if (!S) return MW_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return MW_EINVAL;
+  if (it->second.state == RQ_QUEUED || it->second.state == RQ_RUNNING) return MW_EBUSY;
+  S->pool.release(it->second.out_off, it->second.out_bytes);
+  S->reqs.erase(it);
+  S->cv_work.notify_one();
+  return MW_OK;
+}
+
+extern "C" int mw_server_drain(mw_server_t S) {
+  if (!S) return MW_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->cv_done.wait(lk, [&] { return S->queue.empty() && S->inflight == 0; });
+  return MW_OK;
+}
+
+extern "C" int mw_server_get_stats(mw_server_t S, mw_server_stats* stats) {
+  if (!S || !stats) return MW_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  *stats = S->stats;
+  stats->pool_peak = S->pool.peak();
+  return MW_OK;
+}
+
+extern "C" int mw_server_replay(mw_server_t S, const mw_request* reqs, const double* arrival_us, uint32_t count,
+                                double* latency_us, double* makespan_us) {
+  if (!S || !reqs || !arrival_us || !latency_us || count == 0) return MW_EINVAL;
+  std::vector<uint64_t> tickets(count, 0);
+  std::atomic<uint32_t> submitted{0};
+  std::atomic<int> status{MW_OK};
+  const double t0 = now_us();
+  double last_done = t0;
+  // collector: release every completed request as soon as it is seen
+  std::thread collector([&] {
+    uint32_t done = 0, scan = 0;
+    std::vector<char> seen(count, 0);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (done < count) {
+      const uint32_t ns = submitted.load();
+      bool any = false;
+      for (uint32_t i = scan; i < ns; ++i) {
+        if (seen[i]) continue;
+        auto it = S->reqs.find(tickets[i]);
+        if (it == S->reqs.end()) continue;
+        Req& R = it->second;
+        if (R.state != RQ_DONE && R.state != RQ_FAILED) continue;
+        if (R.state == RQ_FAILED) status = MW_EDEVICE;
+        latency_us[i] = R.t_done - (t0 + arrival_us[i]);
+        last_done = std::max(last_done, R.t_done);
+        S->pool.release(R.out_off, R.out_bytes);
+        S->reqs.erase(it);
+        seen[i] = 1;
+        ++done;
+        any = true;
+      }
+      while (scan < ns && seen[scan]) ++scan;
+      if (any) S->cv_work.notify_one();
+      else S->cv_done.wait_for(lk, std::chrono::microseconds(50));
+    }
+  });
+  for (uint32_t i = 0; i < count; ++i) {
+    const double target = t0 + arrival_us[i];
+    for (;;) {
+      const double d = target - now_us();
+      if (d <= 0) break;
+      if (d > 200) std::this_thread::sleep_for(std::chrono::microseconds((long)(d - 100)));
+    }
+    uint64_t tk = 0;
+    int st = mw_server_submit(S, &reqs[i], &tk);
+    if (st != MW_OK) {
+      status = st;
+      // an invalid request completes immediately as failed so the collector ends
+      std::lock_guard<std::mutex> lk(S->mu);
+      Req R;
+      R.r = reqs[i];
+      R.state = RQ_FAILED;
+      R.t_submit = R.t_done = now_us();
+      tk = S->next_ticket++;
+      S->reqs.emplace(tk, R);
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      tickets[i] = tk;
+    }
+    submitted.store(i + 1);
+  }
+  collector.join();
+  if (makespan_us) *makespan_us = last_done - t0;
+  return status.load();
+}
+
+extern "C" int mw_server_destroy(mw_server_t S) {
+  if (!S) return MW_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv_work.notify_all();
+  }
+  if (S->sched.joinable()) S->sched.join();
+  if (!S->cfg.dry_run) (void)hipDeviceSynchronize();
+  free_server(S);
+  return MW_OK;
+}

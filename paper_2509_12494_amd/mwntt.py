@@ -34,6 +34,28 @@ class NttJob(ctypes.Structure):
                 ("in2", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+MW_REQ_NTT_FORWARD, MW_REQ_NTT_INVERSE, MW_REQ_POLYMUL = 0, 1, 2
+MW_REQ_VEC_ADDMOD, MW_REQ_VEC_SUBMOD, MW_REQ_VEC_MULMOD, MW_REQ_VEC_AXPYMOD = 3, 4, 5, 6
+MW_EBUSY = -7
+
+
+class MwRequest(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("plan", ctypes.c_void_p), ("q", ctypes.c_uint64 * 2),
+                ("limbs", ctypes.c_uint32), ("alpha", ctypes.c_uint64 * 2), ("n", ctypes.c_uint64),
+                ("in_", ctypes.c_void_p), ("in2", ctypes.c_void_p)]
+
+
+class MwServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("dry_run", ctypes.c_uint32)]
+
+
+class MwServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("max_batch_seen", ctypes.c_uint64), ("queue_peak", ctypes.c_uint64),
+                ("inflight_peak", ctypes.c_uint64), ("pool_peak", ctypes.c_size_t)]
+
+
 class MwError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -71,6 +93,17 @@ def lib() -> ctypes.CDLL:
         "ntt_batch_info": (ctypes.c_int, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
         "ntt_batch_check": (ctypes.c_int, [vp]),
         "ntt_batch_destroy": (ctypes.c_int, [vp]),
+        "mw_server_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(MwServerConfig)]),
+        "mw_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(MwRequest), ctypes.POINTER(ctypes.c_uint64)]),
+        "mw_server_result": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(vp),
+                                            ctypes.POINTER(ctypes.c_double)]),
+        "mw_server_release": (ctypes.c_int, [vp, ctypes.c_uint64]),
+        "mw_server_drain": (ctypes.c_int, [vp]),
+        "mw_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(MwServerStats)]),
+        "mw_server_replay": (ctypes.c_int, [vp, ctypes.POINTER(MwRequest), ctypes.POINTER(ctypes.c_double), u32,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "mw_server_destroy": (ctypes.c_int, [vp]),
+        "mw_copy": (ctypes.c_int, [vp, vp, sz, vp]),
         "mw_canonical_root": (ctypes.c_int, [u64p, u32, u32, u64p]),
         "mw_shoup_companion": (ctypes.c_int, [u64p, u64p, u32, u64p]),
         "mw_barrett_mu": (ctypes.c_int, [u64p, u32, u64p]),
@@ -281,6 +314,92 @@ class NttBatch:
             self.destroy()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# serving runtime
+# ---------------------------------------------------------------------------
+def make_request(op: int, inp, inp2=None, plan: Optional[NttPlan] = None, q: int = 0, limbs: int = 0,
+                 n: int = 0, alpha: int = 0) -> MwRequest:
+    r = MwRequest()
+    r.op = op
+    r.plan = plan._h.value if plan is not None else None
+    if plan is None:
+        r.q = _words(q, limbs)
+        r.alpha = _words(alpha, limbs)
+        r.limbs = limbs
+        r.n = n
+    r.in_ = _ptr(inp)
+    r.in2 = _ptr(inp2) if inp2 is not None else None
+    return r
+
+
+class MwServer:
+    """Owning wrapper of an mw_server_t (continuous batching of NTT / BLAS requests)."""
+
+    def __init__(self, hbm_budget: int, max_inflight: int = 4, max_batch: int = 64, dry_run: bool = False):
+        cfg = MwServerConfig(hbm_budget, max_inflight, max_batch, 1 if dry_run else 0)
+        h = ctypes.c_void_p()
+        _check(lib().mw_server_create(ctypes.byref(h), ctypes.byref(cfg)), "mw_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, req: MwRequest, keep=None) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().mw_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "mw_server_submit")
+        if keep is not None:
+            self._keep[t.value] = keep
+        return t.value
+
+    def result(self, ticket: int, wait: bool = True):
+        """(device pointer of the output or None, latency in us); raises MwError (MW_EBUSY if not ready)."""
+        p, lat = ctypes.c_void_p(), ctypes.c_double()
+        _check(lib().mw_server_result(self._h, ticket, 1 if wait else 0, ctypes.byref(p), ctypes.byref(lat)),
+               "mw_server_result")
+        return p.value, lat.value
+
+    def release(self, ticket: int) -> None:
+        _check(lib().mw_server_release(self._h, ticket), "mw_server_release")
+        self._keep.pop(ticket, None)
+
+    def drain(self) -> None:
+        _check(lib().mw_server_drain(self._h), "mw_server_drain")
+
+    def stats(self) -> dict:
+        st = MwServerStats()
+        _check(lib().mw_server_get_stats(self._h, ctypes.byref(st)), "mw_server_get_stats")
+        return {f: getattr(st, f) for f, _ in MwServerStats._fields_}
+
+    def replay(self, reqs, arrival_us):
+        """Open-loop replay; returns (latencies in us, makespan in us)."""
+        n = len(reqs)
+        arr = (MwRequest * n)(*reqs)
+        arrivals = (ctypes.c_double * n)(*arrival_us)
+        lat = (ctypes.c_double * n)()
+        span = ctypes.c_double()
+        _check(lib().mw_server_replay(self._h, arr, arrivals, n, lat, ctypes.byref(span)), "mw_server_replay")
+        return list(lat), span.value
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().mw_server_destroy(self._h), "mw_server_destroy")
+            self._h = None
+            self._keep = {}
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def copy_to_tensor(ptr: int, like, stream=None):
+    """Copy a server-owned device buffer into a new device tensor shaped like `like`."""
+    import torch
+    out = torch.empty_like(like)
+    nbytes = out.numel() * out.element_size()
+    _check(lib().mw_copy(out.data_ptr(), ptr, nbytes, _stream(stream)), "mw_copy")
+    return out
 
 
 # ---------------------------------------------------------------------------
