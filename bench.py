@@ -45,6 +45,11 @@ def percentile(xs, p):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def progress(msg):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def time_calls(fn, stream, reps=20, warm=3):
     """Mean microseconds per call of fn() on `stream` (HIP events)."""
     import torch
@@ -73,6 +78,56 @@ def time_graph(fn, stream, reps=20):
     us = time_calls(g.replay, torch.cuda.current_stream(), reps=reps)
     del g
     return us
+
+
+def serving_leg(count, rate=20000.0, budget=1 << 30):
+    """Open-loop Poisson stream through the serving runtime (inputs pre-staged).
+
+    70% transforms (half forward, half inverse) with N = 2^e, e uniform in
+    10..17; 30% BLAS (half mulmod, half axpymod) with length floor(2^u), u
+    uniform in [10, 17]; 60- or 124-bit moduli with equal probability."""
+    import torch
+    from paper_2509_12494_amd import mwntt
+    from paper_2509_12494_amd import workloads as W
+    jobs = W.serving_stream(count, rate=rate, primes_per_width=2)
+    plans, bufs = {}, {}
+
+    def buf(q, limbs, n, tag):
+        key = (q, n, tag)
+        if key not in bufs:
+            bufs[key] = mwntt.to_device(W.uniform_residues(W.rng(len(bufs) + 77), q, n, limbs))
+        return bufs[key]
+
+    reqs, arrivals = [], []
+    for j in jobs:
+        q, limbs, op = j["q"], j["limbs"], j["op"]
+        if op.startswith("ntt"):
+            lg = j["size"].bit_length() - 1
+            if (lg, q) not in plans:
+                plans[(lg, q)] = mwntt.ntt_plan(lg, q, limbs)
+            plan = plans[(lg, q)]
+            code = mwntt.MW_REQ_NTT_FORWARD if op == "ntt_forward" else mwntt.MW_REQ_NTT_INVERSE
+            reqs.append(mwntt.make_request(code, buf(q, limbs, j["size"], "a"), plan=plan))
+        else:
+            code = mwntt.MW_REQ_VEC_MULMOD if op == "vec_mulmod" else mwntt.MW_REQ_VEC_AXPYMOD
+            a, b = buf(q, limbs, 1 << 17, "a"), buf(q, limbs, 1 << 17, "b")
+            reqs.append(mwntt.make_request(code, a, b, q=q, limbs=limbs, n=j["size"], alpha=(q - 1) // 3))
+        arrivals.append(j["t"] * 1e6)
+    torch.cuda.synchronize()
+    progress(f"serving: {len(plans)} plans, {len(bufs)} input buffers staged")
+    srv = mwntt.MwServer(budget, max_inflight=4, max_batch=64)
+    warm = min(2000, count)
+    srv.replay(reqs[:warm], [a - arrivals[0] for a in arrivals[:warm]])
+    lat, span = srv.replay(reqs, arrivals)
+    st = srv.stats()
+    srv.destroy()
+    for p in plans.values():
+        p.destroy()
+    return {"requests": count, "offered_rate": rate, "hbm_budget": budget,
+            "throughput_req_s": round(count / (span * 1e-6), 1),
+            "p50_us": round(percentile(lat, 50), 2), "p99_us": round(percentile(lat, 99), 2),
+            "mean_us": round(sum(lat) / len(lat), 2), "makespan_s": round(span * 1e-6, 4),
+            "batches": st["batches"] - 0, "max_batch": st["max_batch_seen"], "pool_peak_bytes": st["pool_peak"]}
 
 
 def cpu_baseline(wl, budget_s=12.0):
@@ -104,6 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=96, help="transforms per call in the batched leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=40000,
+                    help="requests in the serving leg (Poisson, 20k requests/s); 0 skips it")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -145,6 +202,7 @@ def main():
         for f in ops.values():
             f()
 
+    progress("plain step")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -181,6 +239,7 @@ def main():
         lat[name] = {"p50_us": round(percentile(us, 50), 3), "p99_us": round(percentile(us, 99), 3),
                      "mean_last_half_us": round(sum(half) / len(half), 3)}
 
+    progress("batched legs")
     # batched leg: many 2^16 transforms in one call (same plan, same q)
     B = args.batch
     bpoly = mwntt.to_device(W.uniform_residues(W.rng(2100), q, n * B, limbs))
@@ -201,7 +260,9 @@ def main():
     mixed = W.config_batched()
     mplans, mjobs, mbfly = {}, [], 0
     for (lg, qm, lm, coeffs) in mixed:
-        pl = mplans.setdefault((lg, qm), mwntt.ntt_plan(lg, qm, lm))
+        if (lg, qm) not in mplans:
+            mplans[(lg, qm)] = mwntt.ntt_plan(lg, qm, lm)
+        pl = mplans[(lg, qm)]
         x = mwntt.to_device(coeffs)
         mjobs.append((pl, mwntt.NTT_JOB_FORWARD, x, None, torch.empty_like(x)))
         mbfly += (1 << (lg - 1)) * lg
@@ -228,6 +289,10 @@ def main():
     fplan.destroy()
     for pl in mplans.values():
         pl.destroy()
+
+    if args.serve_requests:
+        progress(f"serving leg: {args.serve_requests} requests")
+        legs["serving"] = serving_leg(args.serve_requests)
 
     # roofline of the dominant call: the batched forward transform (two kernels:
     # column pass + row pass), ALU-bound
@@ -275,6 +340,7 @@ def main():
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = nbytes
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(wl)
     plan.destroy()
     print(json.dumps(res), flush=True)

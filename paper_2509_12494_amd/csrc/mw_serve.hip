@@ -151,6 +151,10 @@ struct mw_server_s {
   uint32_t inflight = 0;
   mw_server_stats stats{};
   bool stop = false;
+  // completion log for mw_server_replay: while `track_done` is set the
+  // scheduler appends every completed ticket
+  bool track_done = false;
+  std::deque<uint64_t> done_fifo;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::thread sched;
@@ -239,6 +243,7 @@ void scheduler(mw_server_s* S) {
         S->pool.release(R.scratch_off, R.scratch_bytes);
         R.scratch_bytes = 0;
         ++S->stats.completed;
+        if (S->track_done) S->done_fifo.push_back(tk);
       }
       slot.tickets.clear();
       slot.busy = false;
@@ -286,6 +291,7 @@ void scheduler(mw_server_s* S) {
           S->pool.release(R.scratch_off, R.scratch_bytes);
           R.scratch_bytes = 0;
           ++S->stats.completed;
+          if (S->track_done) S->done_fifo.push_back(tk);
         }
         slot->tickets.clear();
         slot->busy = false;
@@ -406,11 +412,11 @@ extern "C" int mw_server_create(mw_server_t* out, const mw_server_config* cfg) {
   return MW_OK;
 }
 
-extern "C" int mw_server_submit(mw_server_t S, const mw_request* request, uint64_t* ticket) {
-  if (!S || !request || !ticket) return MW_EINVAL;
+namespace {
+// Queue a request; the caller holds S->mu.
+int submit_locked(mw_server_s* S, const mw_request* request, uint64_t* ticket) {
   Req R;
   R.r = *request;
-  std::lock_guard<std::mutex> lk(S->mu);
   int st = validate(S, *request, R);
   if (st != MW_OK) return st;
   R.t_submit = now_us();
@@ -422,6 +428,13 @@ extern "C" int mw_server_submit(mw_server_t S, const mw_request* request, uint64
   *ticket = t;
   S->cv_work.notify_one();
   return MW_OK;
+}
+}  // namespace
+
+extern "C" int mw_server_submit(mw_server_t S, const mw_request* request, uint64_t* ticket) {
+  if (!S || !request || !ticket) return MW_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  return submit_locked(S, request, ticket);
 }
 
 extern "C" int mw_server_result(mw_server_t S, uint64_t ticket, int wait, void** d_out, double* latency_us) {
@@ -473,37 +486,41 @@ extern "C" int mw_server_get_stats(mw_server_t S, mw_server_stats* stats) {
 extern "C" int mw_server_replay(mw_server_t S, const mw_request* reqs, const double* arrival_us, uint32_t count,
                                 double* latency_us, double* makespan_us) {
   if (!S || !reqs || !arrival_us || !latency_us || count == 0) return MW_EINVAL;
-  std::vector<uint64_t> tickets(count, 0);
-  std::atomic<uint32_t> submitted{0};
-  std::atomic<int> status{MW_OK};
+  std::unordered_map<uint64_t, uint32_t> index;   // ticket -> request position
+  index.reserve(count * 2);
+  int status = MW_OK;
+  uint32_t done = 0;
   const double t0 = now_us();
   double last_done = t0;
-  // collector: release every completed request as soon as it is seen
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->track_done) return MW_EBUSY;            // one replay at a time
+    S->track_done = true;
+    S->done_fifo.clear();
+  }
+  // collector: releases each completed request as the scheduler reports it
   std::thread collector([&] {
-    uint32_t done = 0, scan = 0;
-    std::vector<char> seen(count, 0);
     std::unique_lock<std::mutex> lk(S->mu);
     while (done < count) {
-      const uint32_t ns = submitted.load();
-      bool any = false;
-      for (uint32_t i = scan; i < ns; ++i) {
-        if (seen[i]) continue;
-        auto it = S->reqs.find(tickets[i]);
-        if (it == S->reqs.end()) continue;
+      if (S->done_fifo.empty()) {
+        S->cv_done.wait_for(lk, std::chrono::microseconds(200));
+        continue;
+      }
+      while (!S->done_fifo.empty()) {
+        const uint64_t tk = S->done_fifo.front();
+        S->done_fifo.pop_front();
+        auto pos = index.find(tk);
+        auto it = S->reqs.find(tk);
+        if (pos == index.end() || it == S->reqs.end()) continue;   // not part of this replay
         Req& R = it->second;
-        if (R.state != RQ_DONE && R.state != RQ_FAILED) continue;
         if (R.state == RQ_FAILED) status = MW_EDEVICE;
-        latency_us[i] = R.t_done - (t0 + arrival_us[i]);
+        latency_us[pos->second] = R.t_done - (t0 + arrival_us[pos->second]);
         last_done = std::max(last_done, R.t_done);
         S->pool.release(R.out_off, R.out_bytes);
         S->reqs.erase(it);
-        seen[i] = 1;
         ++done;
-        any = true;
       }
-      while (scan < ns && seen[scan]) ++scan;
-      if (any) S->cv_work.notify_one();
-      else S->cv_done.wait_for(lk, std::chrono::microseconds(50));
+      S->cv_work.notify_one();
     }
   });
   for (uint32_t i = 0; i < count; ++i) {
@@ -513,28 +530,27 @@ extern "C" int mw_server_replay(mw_server_t S, const mw_request* reqs, const dou
       if (d <= 0) break;
       if (d > 200) std::this_thread::sleep_for(std::chrono::microseconds((long)(d - 100)));
     }
+    std::lock_guard<std::mutex> lk(S->mu);
     uint64_t tk = 0;
-    int st = mw_server_submit(S, &reqs[i], &tk);
-    if (st != MW_OK) {
+    const int st = submit_locked(S, &reqs[i], &tk);
+    if (st == MW_OK) {
+      index.emplace(tk, i);
+    } else {
+      // rejected requests count as failed and complete at once
       status = st;
-      // an invalid request completes immediately as failed so the collector ends
-      std::lock_guard<std::mutex> lk(S->mu);
-      Req R;
-      R.r = reqs[i];
-      R.state = RQ_FAILED;
-      R.t_submit = R.t_done = now_us();
-      tk = S->next_ticket++;
-      S->reqs.emplace(tk, R);
+      latency_us[i] = 0;
+      ++done;
+      S->cv_done.notify_all();
     }
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      tickets[i] = tk;
-    }
-    submitted.store(i + 1);
   }
   collector.join();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->track_done = false;
+    S->done_fifo.clear();
+  }
   if (makespan_us) *makespan_us = last_done - t0;
-  return status.load();
+  return status;
 }
 
 extern "C" int mw_server_destroy(mw_server_t S) {

@@ -113,7 +113,9 @@ def test_paper_mixed_batch_96():
     jobs, plain = [], []
     plans = {}
     for i, (log2n, q, limbs, coeffs) in enumerate(polys):
-        plan = plans.setdefault((log2n, q), mwntt.ntt_plan(log2n, q, limbs))
+        if (log2n, q) not in plans:
+            plans[(log2n, q)] = mwntt.ntt_plan(log2n, q, limbs)
+        plan = plans[(log2n, q)]
         x = dev(coeffs)
         y = torch.empty_like(x)
         jobs.append((plan, mwntt.NTT_JOB_FORWARD, x, None, y))

@@ -29,7 +29,9 @@ def _workload(count, seed, log2_range=(10, 13)):
         if op <= mwntt.MW_REQ_POLYMUL:
             log2n = int(g.integers(log2_range[0], log2_range[1] + 1))
             n = 1 << log2n
-            plan = plans.setdefault((log2n, q), mwntt.ntt_plan(log2n, q, limbs))
+            if (log2n, q) not in plans:
+                plans[(log2n, q)] = mwntt.ntt_plan(log2n, q, limbs)
+            plan = plans[(log2n, q)]
         else:
             n = int(2.0 ** g.uniform(log2_range[0], log2_range[1]))
             plan = None
