@@ -32,6 +32,35 @@ INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # with W words: quotient estimate from the W(W+1)/2 top-column partial
 # products, W(W+1)/2 each for the low halves of x*w and Q*q, W word subs for
 # the remainder, and 2W word add/sub for the butterfly's sum and difference).
+PROFILE = os.path.join(ROOT, "profiles", "ntt_fwd_2e16_124bit_b64.md")
+KERNEL_SOURCES = ["mw_arith.h", "mw_ntt_tile.h", "mw_ntt_kernels.inc", "mw_ntt.hip", "mw_tuned.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2509_12494_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(pass_):
+    """HBM bytes per launch of the pass from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy of known size), or None
+    when the summary is missing or the kernel sources changed since."""
+    try:
+        lines = open(PROFILE).read().splitlines()
+    except OSError:
+        return None
+    kv = dict(l.split(":", 1) for l in lines if l.startswith("- ") and ":" in l)
+    kv = {k[2:].strip(): v.strip() for k, v in kv.items()}
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    v = kv.get(f"traffic_bytes_pass{pass_}")
+    return int(v) if v else None
+
+
 def butterfly_word_ops(W):
     return 3 * (W * (W + 1) // 2) + W + 2 * W
 
@@ -294,12 +323,32 @@ def main():
         progress(f"serving leg: {args.serve_requests} requests")
         legs["serving"] = serving_leg(args.serve_requests)
 
-    # roofline of the dominant call: the batched forward transform (two kernels:
-    # column pass + row pass), ALU-bound
+    # roofline of the dominant kernel: the two passes of the batched forward
+    # transform, each one kernel launch, timed with HIP events on their stream
+    progress("roofline passes")
+    RB = min(64, B)
+    rin, rout = bpoly[:RB * n], bspec[:RB * n]
+    ref = torch.empty_like(rin)
+    plan.forward(ref, rin, batch=RB, stream=sp)
+    plan.forward_pass(1, None, rin, RB, stream=sp)
+    plan.forward_pass(2, rout, None, RB, stream=sp)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, rout), "pass 1 + pass 2 differs from ntt_forward"
+    split = plan.split
     W_words = 2 * limbs
     bfly = (n // 2) * log2n
-    ops_per_call = B * bfly * butterfly_word_ops(W_words)
-    achieved_tops = ops_per_call / (batched_us * 1e-6) / 1e12
+    passes = {}
+    for k, (stages, fn) in {1: (split, lambda: plan.forward_pass(1, None, rin, RB, stream=sp)),
+                            2: (log2n - split, lambda: plan.forward_pass(2, rout, None, RB, stream=sp))}.items():
+        us = time_calls(fn, stream, reps=50)
+        ops = RB * (n // 2) * stages * butterfly_word_ops(W_words)
+        tw_bytes = (1 << split if k == 1 else n) * 32 * limbs // 2
+        byts = 2 * RB * n * 8 * limbs + tw_bytes
+        passes[k] = {"us": us, "ops": ops, "bytes": byts}
+    dom = max(passes, key=lambda k: passes[k]["us"])
+    d = passes[dom]
+    achieved_tops = d["ops"] / (d["us"] * 1e-6) / 1e12
+    traffic = measured_traffic(dom)
 
     mulmods_step = 2 * bfly + 2 * n        # two transforms + vec_mulmod + vec_axpymod
     res = {
@@ -324,10 +373,15 @@ def main():
                     "speedup_vs_plain_forward": round(batched_ntt_s / (1e6 / lat["ntt_forward"]["p50_us"]), 2),
                     "gmulmod_s": round(B * bfly / (batched_us * 1e-6) / 1e9, 3)},
         "legs": legs,
-        "roofline": {"bound": "alu", "kernel": "ntt_forward batched (column + row pass kernels)",
+        "roofline": {"bound": "alu",
+                     "kernel": f"forward pass {dom} ({'column' if dom == 1 else 'row'} tiles), N=2^16, 124-bit, "
+                               f"batch {RB}, one launch",
                      "achieved": round(achieved_tops, 3), "peak": round(INT32_PEAK_TOPS, 2),
-                     "unit": "Tint32op/s", "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": None,
-                     "ops_per_butterfly": butterfly_word_ops(W_words)},
+                     "unit": "Tint32op/s", "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": traffic,
+                     "launch_us": round(d["us"], 3), "ops_per_butterfly": butterfly_word_ops(W_words),
+                     "algorithmic_bytes": d["bytes"],
+                     "hbm_gbs_algorithmic": round(d["bytes"] / (d["us"] * 1e-6) / 1e9, 1),
+                     "passes_us": {str(k): round(v["us"], 3) for k, v in passes.items()}},
         "wall_s_timed_region": round(wall, 4),
     }
     if args.copy_calibration_mib:

@@ -137,6 +137,15 @@ int ntt_plan_get_tiles(ntt_plan_t plan, uint32_t pass, uint32_t* log_p, uint32_t
 int ntt_forward(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, void* stream);
 int ntt_inverse(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, void* stream);
 
+/* One pass of a two-pass forward transform, for callers that schedule the
+ * passes themselves (or time them separately): pass 1 runs the first log N1
+ * stages (column tiles) from d_in into the plan's scratch, pass 2 the
+ * remaining stages (row tiles) from the scratch into d_out, in the order the
+ * plan's flags give.  Running pass 1 then pass 2 with the same batch equals
+ * ntt_forward.  MW_EINVAL if the plan's configuration for this batch is a
+ * single-workgroup transform; MW_ESIZE if the batch exceeds the scratch. */
+int ntt_forward_pass(ntt_plan_t plan, uint32_t pass, void* d_out, const void* d_in, uint32_t batch, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched executor: many jobs -- forward or inverse transforms, or fused     */
 /* negacyclic products c = INTT(NTT(a) * NTT(b)) (Background, polynomial     */

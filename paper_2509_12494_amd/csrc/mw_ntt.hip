@@ -369,6 +369,51 @@ extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint
   return MW_OK;
 }
 
+namespace {
+template <int W>
+int run_pass(ntt_plan_s* P, uint32_t pass, void* d_out, const void* d_in, uint32_t batch, hipStream_t s) {
+  const PlanConfig& C = pick_config(P, batch);
+  if (C.log_n1 == 0) return MW_EINVAL;
+  if (batch > P->scratch_polys) return MW_ESIZE;
+  NttParams<W> p = {};
+  p.tw = reinterpret_cast<const Tw<W>*>(P->d_tw_fwd);
+  if constexpr (W == 4) {
+    p.M = P->M4;
+  } else {
+    p.M = P->M2;
+  }
+  p.log_n = P->log2n;
+  p.log_n1 = C.log_n1;
+  p.batch = batch;
+  Res<W>* scr = reinterpret_cast<Res<W>*>(P->d_scratch);
+  hipError_t e;
+  if (pass == 1) {
+    p.src = reinterpret_cast<const Res<W>*>(d_in);
+    p.dst = scr;
+    p.permute = 0;
+    e = launch_pass<W>(DIR_FWD, MODE_COL, P, C, p,
+                       batch * tiles_per_poly<MODE_COL>(P->log2n, C.log_n1, C.cfg[MODE_COL].lines), s);
+  } else {
+    p.src = scr;
+    p.dst = reinterpret_cast<Res<W>*>(d_out);
+    p.permute = !(P->flags & NTT_BITREV_OUT);
+    e = launch_pass<W>(DIR_FWD, MODE_ROW, P, C, p,
+                       batch * tiles_per_poly<MODE_ROW>(P->log2n, C.log_n1, C.cfg[MODE_ROW].lines), s);
+  }
+  return e == hipSuccess ? MW_OK : MW_EDEVICE;
+}
+}  // namespace
+
+extern "C" int ntt_forward_pass(ntt_plan_t plan, uint32_t pass, void* d_out, const void* d_in, uint32_t batch,
+                                void* stream) {
+  if (!plan || (pass != 1 && pass != 2)) return MW_EINVAL;
+  if (batch == 0) return MW_OK;
+  if ((pass == 1 && !d_in) || (pass == 2 && !d_out)) return MW_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return plan->limbs == 2 ? run_pass<4>(plan, pass, d_out, d_in, batch, s)
+                          : run_pass<2>(plan, pass, d_out, d_in, batch, s);
+}
+
 extern "C" int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1) {
   if (!plan) return MW_EINVAL;
   const uint32_t max_full = plan->limbs == 2 ? kMaxFullLog4 : kMaxFullLog2;

@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
         "ntt_plan_set_tiles": (ctypes.c_int, [vp, u32, u32, u32]),
         "ntt_plan_get_tiles": (ctypes.c_int, [vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
         "ntt_forward": (ctypes.c_int, [vp, vp, vp, u32, vp]),
+        "ntt_forward_pass": (ctypes.c_int, [vp, u32, vp, vp, u32, vp]),
         "ntt_inverse": (ctypes.c_int, [vp, vp, vp, u32, vp]),
         "ntt_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(NttJob), u32]),
         "ntt_batch_run": (ctypes.c_int, [vp, vp]),
@@ -249,6 +250,12 @@ class NttPlan:
     def forward(self, out, inp, batch: Optional[int] = None, stream=None) -> None:
         b = self._batch(inp, batch)
         _check(lib().ntt_forward(self._h, _ptr(out), _ptr(inp), b, _stream(stream)), "ntt_forward")
+
+    def forward_pass(self, pass_: int, out, inp, batch: int, stream=None) -> None:
+        """Pass 1 (column tiles, inp -> plan scratch) or 2 (row tiles, scratch -> out)."""
+        o = _ptr(out) if out is not None else None
+        i = _ptr(inp) if inp is not None else None
+        _check(lib().ntt_forward_pass(self._h, pass_, o, i, batch, _stream(stream)), "ntt_forward_pass")
 
     def inverse(self, out, inp, batch: Optional[int] = None, stream=None) -> None:
         b = self._batch(inp, batch)

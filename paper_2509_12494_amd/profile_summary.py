@@ -1,0 +1,96 @@
+"""Summaries of rocprofv3 result databases (SQLite files written by
+`rocprofv3 -d DIR -o NAME ...`).
+
+    python -m paper_2509_12494_amd.profile_summary kernels RESULTS.db [--match mw::] [--top N]
+    python -m paper_2509_12494_amd.profile_summary counters FETCH.db WRITE.db --copy-bytes BYTES [--match mw::] [--top N]
+
+`kernels` lists every kernel (grouped by name and grid size) with its launch
+count and average / min / max duration.  `counters` reads FETCH_SIZE and
+WRITE_SIZE (KiB per dispatch) from two separate counter runs and converts them
+to bytes with the factor that makes the largest device-to-device copy kernel
+of the run (`__amd_rocclr_copyBuffer`, BYTES long) read and write exactly BYTES.
+"""
+import argparse
+import sqlite3
+import sys
+
+
+def _short(name):
+    n = name.split("(")[0]
+    return n.replace("void ", "")
+
+
+def kernels(db, match=None):
+    con = sqlite3.connect(db)
+    q = ("select name, grid_x, workgroup_x, count(*), avg(duration), min(duration), max(duration) "
+         "from kernels group by name, grid_x order by avg(duration)*count(*) desc")
+    rows = []
+    for name, grid, wg, n, avg, mn, mx in con.execute(q):
+        if match and match not in name:
+            continue
+        rows.append((_short(name), grid // max(wg, 1), wg, n, avg / 1e3, mn / 1e3, mx / 1e3))
+    return rows
+
+
+def _counter(db, counter):
+    con = sqlite3.connect(db)
+    q = ("select kernel_name, grid_size, workgroup_size, avg(value), count(*) from counters_collection "
+         "where counter_name = ? group by kernel_name, grid_size")
+    return [(k, g // max(w, 1), v * 1024.0, n) for k, g, w, v, n in con.execute(q, (counter,))]
+
+
+def counters(fetch_db, write_db, copy_bytes, match=None):
+    fetch = _counter(fetch_db, "FETCH_SIZE")
+    write = _counter(write_db, "WRITE_SIZE")
+
+    def scale(rows):
+        copies = [r for r in rows if "copyBuffer" in r[0]]
+        big = max(copies, key=lambda r: r[2])
+        return copy_bytes / big[2], big[2]
+    fs, fraw = scale(fetch)
+    ws, wraw = scale(write)
+    wmap = {(k, g): v for k, g, v, _ in write}
+    out = []
+    for k, g, v, n in fetch:
+        if match and match not in k:
+            continue
+        w = wmap.get((k, g))
+        out.append((_short(k), g, n, v * fs, (w or 0) * ws))
+    out.sort(key=lambda r: -(r[3] + r[4]) * r[2])
+    return {"fetch_factor": fs, "write_factor": ws, "copy_fetch_raw": fraw, "copy_write_raw": wraw, "rows": out}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("kernels")
+    a.add_argument("db")
+    a.add_argument("--match", default=None)
+    a.add_argument("--top", type=int, default=None)
+    b = sub.add_parser("counters")
+    b.add_argument("fetch_db")
+    b.add_argument("write_db")
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--match", default=None)
+    b.add_argument("--top", type=int, default=None)
+    args = ap.parse_args(argv)
+    if args.cmd == "kernels":
+        print("| kernel | workgroups | threads | launches | avg us | min us | max us |")
+        print("|---|---|---|---|---|---|---|")
+        for r in kernels(args.db, args.match)[:args.top]:
+            print(f"| `{r[0]}` | {r[1]} | {r[2]} | {r[3]} | {r[4]:.3f} | {r[5]:.3f} | {r[6]:.3f} |")
+    else:
+        c = counters(args.fetch_db, args.write_db, args.copy_bytes, args.match)
+        print(f"calibration copy of {args.copy_bytes} B: FETCH_SIZE read {c['copy_fetch_raw']:.0f} B "
+              f"(factor {c['fetch_factor']:.3f}), WRITE_SIZE read {c['copy_write_raw']:.0f} B "
+              f"(factor {c['write_factor']:.3f})")
+        print()
+        print("| kernel | workgroups | dispatches | fetch bytes (scaled) | write bytes (scaled) |")
+        print("|---|---|---|---|---|")
+        for k, g, n, f, w in c["rows"][:args.top]:
+            print(f"| `{k}` | {g} | {n} | {f:.0f} | {w:.0f} |")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -251,3 +251,21 @@ def test_impulses(bits, seed):
         ks = [0, 5, n - 1]
         assert [y[k] for k in ks] == [pow(psi, j * (2 * k + 1), q) for k in ks]
     plan.destroy()
+
+
+@pytest.mark.parametrize("bits,seed", WIDTHS)
+@pytest.mark.parametrize("log2n,batch", [(14, 3), (16, 8)])
+def test_forward_passes_equal_forward(log2n, batch, bits, seed):
+    require_gpu()
+    import torch
+    q, limbs, A = _case(bits, seed, log2n, batch)
+    plan = mwntt.ntt_plan(log2n, q, limbs)
+    x = dev(A)
+    ref, out = torch.empty_like(x), torch.empty_like(x)
+    announce("passes", log2n, batch, bits)
+    plan.forward(ref, x, batch=batch)
+    plan.forward_pass(1, None, x, batch)
+    plan.forward_pass(2, out, None, batch)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, out)
+    plan.destroy()
