@@ -285,6 +285,50 @@ def main():
                                  "executor_ntt_s": round(B / (exec_us * 1e-6), 1)}}
     ex.destroy()
 
+    # batch sweep of the same transform (inputs: the 96 staged polynomials
+    # repeated, all canonical residues)
+    progress("batch sweep")
+    sweep_max = 1024
+    reps_in = (sweep_max + B - 1) // B
+    sw_in = bpoly.repeat(reps_in, 1)[:sweep_max * n]
+    sw_out = torch.empty_like(sw_in)
+    sweep = {}
+    for bs in (1, 8, 32, 96, 256, 1024):
+        us = time_calls(lambda: plan.forward(sw_out, sw_in, batch=bs, stream=sp), stream, reps=10 if bs >= 256 else 20)
+        sweep[str(bs)] = {"us_per_call": round(us, 2), "ntt_s": round(bs / (us * 1e-6), 1)}
+    legs["batch_sweep_2e16"] = sweep
+    del sw_in, sw_out
+
+    # host-inclusive form (the paper's CPU timings include data transfer):
+    # pinned host input -> device, forward transform, device -> pinned host
+    progress("host-inclusive")
+    h_in = torch.empty(poly.shape, dtype=poly.dtype, pin_memory=True)
+    h_in.copy_(poly)
+    h_out = torch.empty_like(h_in, pin_memory=True)
+    d_in = torch.empty_like(poly)
+    d_out = torch.empty_like(poly)
+
+    def host_round():
+        d_in.copy_(h_in, non_blocking=True)
+        plan.forward(d_out, d_in, batch=1, stream=sp)
+        h_out.copy_(d_out, non_blocking=True)
+    host_us = time_calls(host_round, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(h_out, spec.cpu()), "host-inclusive forward differs"
+    hb_in = torch.empty(bpoly.shape, dtype=bpoly.dtype, pin_memory=True)
+    hb_in.copy_(bpoly)
+    hb_out = torch.empty_like(hb_in, pin_memory=True)
+
+    def host_round_b():
+        bpoly.copy_(hb_in, non_blocking=True)
+        plan.forward(bspec, bpoly, batch=B, stream=sp)
+        hb_out.copy_(bspec, non_blocking=True)
+    host_b_us = time_calls(host_round_b, stream, reps=10)
+    legs["host_inclusive_2e16"] = {"ntt_forward_us": round(host_us, 2), "ntt_s": round(1 / (host_us * 1e-6), 1),
+                                   "batch": B, "batched_us": round(host_b_us, 2),
+                                   "batched_ntt_s": round(B / (host_b_us * 1e-6), 1),
+                                   "bytes_per_transform": 2 * n * 8 * limbs}
+
     # mixed batch: 96 polynomials, N uniform over 2^12..2^16, 60/124-bit, forward
     mixed = W.config_batched()
     mplans, mjobs, mbfly = {}, [], 0
@@ -297,7 +341,18 @@ def main():
         mbfly += (1 << (lg - 1)) * lg
     mb = mwntt.NttBatch(mjobs)
     mixed_us = time_graph(lambda s_: mb.run(stream=s_), stream)
+    # the round trip: a second batch inverts every spectrum
+    mb.run(stream=sp)
+    ijobs = [(pl, mwntt.NTT_JOB_INVERSE, o, None, torch.empty_like(o)) for (pl, _, _, _, o) in mjobs]
+    mi = mwntt.NttBatch(ijobs)
+    mi.run(stream=sp)
+    torch.cuda.synchronize()
+    for (_, _, x, _, _), (_, _, _, _, r) in zip(mjobs, ijobs):
+        assert torch.equal(x, r), "mixed round trip failed"
+    mixed_inv_us = time_graph(lambda s_: mi.run(stream=s_), stream)
+    mi.destroy()
     legs["mixed_96"] = {"polys": len(mixed), "us_per_run": round(mixed_us, 2),
+                        "inverse_us_per_run": round(mixed_inv_us, 2),
                         "polys_s": round(len(mixed) / (mixed_us * 1e-6), 1),
                         "gbutterfly_s": round(mbfly / (mixed_us * 1e-6) / 1e9, 2)}
     mb.destroy()

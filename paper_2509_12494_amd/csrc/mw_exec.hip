@@ -100,6 +100,13 @@ __global__ __launch_bounds__(kExecThreads) void exec_kernel(ExecParams ep) {
   else run_item<2, kLogP2>(ep, J, job, phase, tile, mw_exec_smem);
 }
 
+// host twin of xcd_tile: the tile that position b of a run of n tiles takes
+static u32 xcd_order(u32 b, u32 n) {
+  const u32 full = n - n % 8;
+  if (b >= full) return b;
+  return (b % 8) * (full / 8) + b / 8;
+}
+
 static size_t npad_of(u32 logl, u32 logp) {
   const size_t L = (size_t)1 << logl;
   return (logl > logp ? L + (L >> logp) : L) + 1;
@@ -164,12 +171,24 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
   }
   for (size_t l : out.phase_lds)
     if (l > 160 * 1024) return MW_ESIZE;
-  // tiles, phase-major: launch k covers [phase_begin[k], phase_begin[k+1])
+  // tiles, phase-major: launch k covers [phase_begin[k], phase_begin[k+1]).
+  // Workgroup b of a launch runs on XCD b mod 8 and each XCD has its own L2;
+  // neighbouring column tiles read parts of the same cache lines, so a job's
+  // run of column tiles is laid out such that consecutive tiles share an XCD
+  // (the order xcd_tile gives).  Row tiles keep their order: the tiles that
+  // write one output line are already a multiple of 8 apart.
   for (u32 ph = 0; ph < 3; ++ph) {
     out.phase_begin[ph] = (u32)out.items.size();
-    for (uint32_t i = 0; i < count; ++i)
-      if (ph < out.jobs[i].nphases)
-        for (u32 t = 0; t < out.jobs[i].tiles[ph]; ++t) out.items.push_back(make_uint2(i, (ph << 16) | t));
+    for (uint32_t i = 0; i < count; ++i) {
+      const JobDesc& d = out.jobs[i];
+      if (ph >= d.nphases) continue;
+      const bool col = d.op == JOB_FWD ? ph == 0 : (d.op == JOB_INV ? ph == 1 : ph != 1);
+      const u32 n = d.tiles[ph];
+      for (u32 b = 0; b < n; ++b) {
+        const u32 t = col ? xcd_order(b, n) : b;
+        out.items.push_back(make_uint2(i, (ph << 16) | t));
+      }
+    }
     if (out.items.size() > out.phase_begin[ph]) out.nphases = ph + 1;
   }
   out.phase_begin[3] = (u32)out.items.size();

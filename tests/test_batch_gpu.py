@@ -179,6 +179,43 @@ def test_paper_fused_products_256():
     batch.destroy()
 
 
+@pytest.mark.parametrize("bits", [60, 124])
+def test_largest_length_all_ops(bits):
+    """N = 2^17 (the largest length the serving stream draws): forward, inverse
+    and product jobs in one batch, against the plain entry points and sampled
+    oracle outputs."""
+    require_gpu()
+    import torch
+    plan = _plan(17, bits, 43)
+    q, limbs, n = plan.q, plan.limbs, plan.n
+    g = W.rng(600 + bits)
+    A = W.uniform_residues(g, q, n, limbs)
+    B = W.uniform_residues(g, q, n, limbs)
+    a, b = dev(A), dev(B)
+    fo, io, mo = torch.empty_like(a), torch.empty_like(a), torch.empty_like(a)
+    batch = mwntt.NttBatch([(plan, mwntt.NTT_JOB_FORWARD, a, None, fo), (plan, mwntt.NTT_JOB_INVERSE, a, None, io),
+                            (plan, mwntt.NTT_JOB_POLYMUL, a, b, mo)])
+    announce("batch 2^17", bits, batch.info())
+    batch.run()
+    batch.check()
+    ref = torch.empty_like(a)
+    plan.forward(ref, a)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, fo)
+    plan.inverse(ref, a)
+    torch.cuda.synchronize()
+    assert torch.equal(ref, io)
+    a_i, b_i = W.to_ints(A), W.to_ints(B)
+    ks = [0, 1, n // 2, n - 1, 77777]
+    got = host_ints(fo, limbs)
+    assert [got[k] for k in ks] == oracle.ntt.forward_at(a_i, q, ks)
+    got = host_ints(io, limbs)
+    assert [got[k] for k in ks] == oracle.ntt.inverse_at(a_i, q, ks)
+    got = host_ints(mo, limbs)
+    assert [got[k] for k in ks[:3]] == oracle.polymul.negacyclic_at(a_i, b_i, q, ks[:3])
+    batch.destroy()
+
+
 def test_batch_argument_errors():
     require_gpu()
     import torch
