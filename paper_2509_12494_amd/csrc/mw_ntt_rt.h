@@ -138,27 +138,32 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
   else b_lo = tile;
 
   // ---- device memory -> LDS ----
+  constexpr int P = 1 << LOGP;
+  const auto in_tile = [&](u32 e) { return e < nelem; };
   if (MODE == MODE_COL) {
     const u64 N2 = (u64)1 << log_n2;
-    for (u32 e = t; e < nelem; e += nthreads) {
-      const u32 r = e >> log_lines, c = e & (lines - 1);
-      lds[c * npad + rt_pad<LOGP>(r, logl)] = ResIO<W>::load(p.src + r * N2 + c0 + c);
-    }
+    copy_staged<W, P>(
+        t, nthreads, in_tile,
+        [&](u32 e) { return ResIO<W>::load(p.src + (e >> log_lines) * N2 + c0 + (e & (lines - 1))); },
+        [&](u32 e, const Res<W>& v) { lds[(e & (lines - 1)) * npad + rt_pad<LOGP>(e >> log_lines, logl)] = v; });
   } else {
     const u32 n1_over_g = (1u << log_n1) >> log_lines;
     if (DIR == DIR_INV && p.permute) {
       const u32 col = brev(b_lo, log_n1 - log_lines) << log_lines;
-      for (u32 e = t; e < nelem; e += nthreads) {
-        const u32 lp = e >> log_lines, jj = e & (lines - 1);
-        lds[brev(jj, log_lines) * npad + rt_pad<LOGP>(brev(lp, logl), logl)] =
-            ResIO<W>::load(p.src + ((u64)lp << log_n1) + col + jj);
-      }
+      copy_staged<W, P>(
+          t, nthreads, in_tile,
+          [&](u32 e) { return ResIO<W>::load(p.src + ((u64)(e >> log_lines) << log_n1) + col + (e & (lines - 1))); },
+          [&](u32 e, const Res<W>& v) {
+            lds[brev(e & (lines - 1), log_lines) * npad + rt_pad<LOGP>(brev(e >> log_lines, logl), logl)] = v;
+          });
     } else {
-      for (u32 e = t; e < nelem; e += nthreads) {
-        const u32 j = e >> logl, l = e & (L - 1);
-        const u32 b = j * n1_over_g + b_lo;
-        lds[j * npad + rt_pad<LOGP>(l, logl)] = ResIO<W>::load(p.src + ((u64)b << logl) + l);
-      }
+      copy_staged<W, P>(
+          t, nthreads, in_tile,
+          [&](u32 e) {
+            const u32 b = (e >> logl) * n1_over_g + b_lo;
+            return ResIO<W>::load(p.src + ((u64)b << logl) + (e & (L - 1)));
+          },
+          [&](u32 e, const Res<W>& v) { lds[(e >> logl) * npad + rt_pad<LOGP>(e & (L - 1), logl)] = v; });
     }
   }
   __syncthreads();
@@ -172,25 +177,29 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
   // ---- LDS -> device memory ----
   if (MODE == MODE_COL) {
     const u64 N2 = (u64)1 << log_n2;
-    for (u32 e = t; e < nelem; e += nthreads) {
-      const u32 r = e >> log_lines, c = e & (lines - 1);
-      ResIO<W>::store(p.dst + r * N2 + c0 + c, lds[c * npad + rt_pad<LOGP>(r, logl)]);
-    }
+    copy_staged<W, P>(
+        t, nthreads, in_tile,
+        [&](u32 e) { return lds[(e & (lines - 1)) * npad + rt_pad<LOGP>(e >> log_lines, logl)]; },
+        [&](u32 e, const Res<W>& v) { ResIO<W>::store(p.dst + (e >> log_lines) * N2 + c0 + (e & (lines - 1)), v); });
   } else {
     const u32 n1_over_g = (1u << log_n1) >> log_lines;
     if (DIR == DIR_FWD && p.permute) {
       const u32 col = brev(b_lo, log_n1 - log_lines) << log_lines;
-      for (u32 e = t; e < nelem; e += nthreads) {
-        const u32 lp = e >> log_lines, jj = e & (lines - 1);
-        ResIO<W>::store(p.dst + ((u64)lp << log_n1) + col + jj,
-                        lds[brev(jj, log_lines) * npad + rt_pad<LOGP>(brev(lp, logl), logl)]);
-      }
+      copy_staged<W, P>(
+          t, nthreads, in_tile,
+          [&](u32 e) {
+            return lds[brev(e & (lines - 1), log_lines) * npad + rt_pad<LOGP>(brev(e >> log_lines, logl), logl)];
+          },
+          [&](u32 e, const Res<W>& v) {
+            ResIO<W>::store(p.dst + ((u64)(e >> log_lines) << log_n1) + col + (e & (lines - 1)), v);
+          });
     } else {
-      for (u32 e = t; e < nelem; e += nthreads) {
-        const u32 j = e >> logl, l = e & (L - 1);
-        const u32 b = j * n1_over_g + b_lo;
-        ResIO<W>::store(p.dst + ((u64)b << logl) + l, lds[j * npad + rt_pad<LOGP>(l, logl)]);
-      }
+      copy_staged<W, P>(
+          t, nthreads, in_tile, [&](u32 e) { return lds[(e >> logl) * npad + rt_pad<LOGP>(e & (L - 1), logl)]; },
+          [&](u32 e, const Res<W>& v) {
+            const u32 b = (e >> logl) * n1_over_g + b_lo;
+            ResIO<W>::store(p.dst + ((u64)b << logl) + (e & (L - 1)), v);
+          });
     }
   }
 }
@@ -221,11 +230,29 @@ __device__ __forceinline__ void rt_fused_row(const NttParams<W>& pf, const NttPa
   Res<W>* la = lds;
   Res<W>* lb = lds + lines * npad;
 
-  for (u32 e = t; e < nelem; e += nthreads) {
-    const u32 j = e >> logl, l = e & (L - 1);
-    const u64 off = ((u64)(row0 + j) << logl) + l;
-    la[j * npad + rt_pad<LOGP>(l, logl)] = ResIO<W>::load(pf.src + off);
-    lb[j * npad + rt_pad<LOGP>(l, logl)] = ResIO<W>::load(src2 + off);
+  constexpr int P = 1 << LOGP;
+  const auto in_tile = [&](u32 e) { return e < nelem; };
+  const auto off = [&](u32 e) { return ((u64)(row0 + (e >> logl)) << logl) + (e & (L - 1)); };
+  const auto slot = [&](u32 e) { return (e >> logl) * npad + rt_pad<LOGP>(e & (L - 1), logl); };
+  {
+    // all 2P loads of a and b in flight before the first LDS write
+    Res<W> va[P], vb[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const u32 e = t + (u32)k * nthreads;
+      if (in_tile(e)) {
+        va[k] = ResIO<W>::load(pf.src + off(e));
+        vb[k] = ResIO<W>::load(src2 + off(e));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const u32 e = t + (u32)k * nthreads;
+      if (in_tile(e)) {
+        la[slot(e)] = va[k];
+        lb[slot(e)] = vb[k];
+      }
+    }
   }
   __syncthreads();
   const u32 base = (1u << log_n1) + row0 + line_id;
@@ -238,10 +265,9 @@ __device__ __forceinline__ void rt_fused_row(const NttParams<W>& pf, const NttPa
   }
   __syncthreads();
   rt_line_stages<W, LOGP, DIR_INV>(la + line_id * npad, active, logl, lane, base, pi.tw, pi, false, false);
-  for (u32 e = t; e < nelem; e += nthreads) {
-    const u32 j = e >> logl, l = e & (L - 1);
-    ResIO<W>::store(pf.dst + ((u64)(row0 + j) << logl) + l, la[j * npad + rt_pad<LOGP>(l, logl)]);
-  }
+  copy_staged<W, P>(
+      t, nthreads, in_tile, [&](u32 e) { return la[slot(e)]; },
+      [&](u32 e, const Res<W>& v) { ResIO<W>::store(pf.dst + off(e), v); });
 }
 
 }  // namespace mw

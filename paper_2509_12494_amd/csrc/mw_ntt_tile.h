@@ -149,6 +149,27 @@ __device__ __forceinline__ u32 xcd_tile(u32 b, u32 n) {
   return (b % kXcds) * (full / kXcds) + b / kXcds;
 }
 
+// Tile <-> LDS copies.  Thread t moves elements e = t + k*nthreads for
+// k < P (a tile of `lines` lines of L points moved by lines*L/P threads is
+// exactly P elements per thread; the run-time engine may have fewer).  All P
+// reads are issued before the first write, so the P device-memory loads (or
+// LDS reads) of a thread are in flight together instead of one at a time.
+// rd(e) reads element e, wr(e, v) writes it; ok(e) guards both.
+template <int W, int P, class Ok, class Rd, class Wr>
+__device__ __forceinline__ void copy_staged(u32 t, u32 nthreads, Ok ok, Rd rd, Wr wr) {
+  Res<W> v[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const u32 e = t + (u32)k * nthreads;
+    if (ok(e)) v[k] = rd(e);
+  }
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const u32 e = t + (u32)k * nthreads;
+    if (ok(e)) wr(e, v[k]);
+  }
+}
+
 template <int LOGL, int LOGP>
 struct LineShape {
   static constexpr int L = 1 << LOGL;
@@ -281,37 +302,45 @@ __device__ __forceinline__ void ntt_tile(const NttParams<W>& p, Res<W>* lds, u32
   }
 
   // ---- device memory -> LDS ----
+  // lines * L/P threads move lines * L elements: exactly P each, no guard
+  constexpr int P = S::P;
+  const auto all = [](u32) { return true; };
   if (MODE == MODE_FULL) {
-    for (u32 e = t; e < nelem; e += T) {
-      const u32 ln = e >> LOGL, j = e & (L - 1);
-      const u64 pl = (u64)poly * lines + ln;
-      if (pl < p.batch) {
-        const u32 dj = (DIR == DIR_INV && p.permute) ? brev(j, LOGL) : j;
-        lds[ln * S::NPAD + pad_idx<LOGL, LOGP>(dj)] = ResIO<W>::load(p.src + pl * N + j);
-      }
-    }
+    copy_staged<W, P>(
+        t, T, [&](u32 e) { return e < nelem && (u64)poly * lines + (e >> LOGL) < p.batch; },
+        [&](u32 e) { return ResIO<W>::load(p.src + ((u64)poly * lines + (e >> LOGL)) * N + (e & (L - 1))); },
+        [&](u32 e, const Res<W>& v) {
+          const u32 j = e & (L - 1);
+          const u32 dj = (DIR == DIR_INV && p.permute) ? brev(j, LOGL) : j;
+          lds[(e >> LOGL) * S::NPAD + pad_idx<LOGL, LOGP>(dj)] = v;
+        });
   } else if (MODE == MODE_COL) {
     const u64 N2 = (u64)1 << log_n2;
-    for (u32 e = t; e < nelem; e += T) {
-      const u32 r = e >> log_lines, c = e & (lines - 1);
-      lds[c * S::NPAD + pad_idx<LOGL, LOGP>(r)] = ResIO<W>::load(p.src + (u64)poly * N + r * N2 + c0 + c);
-    }
+    copy_staged<W, P>(
+        t, T, all,
+        [&](u32 e) { return ResIO<W>::load(p.src + (u64)poly * N + (e >> log_lines) * N2 + c0 + (e & (lines - 1))); },
+        [&](u32 e, const Res<W>& v) { lds[(e & (lines - 1)) * S::NPAD + pad_idx<LOGL, LOGP>(e >> log_lines)] = v; });
   } else {
     const u32 n1_over_g = (1u << log_n1) >> log_lines;
     if (DIR == DIR_INV && p.permute) {
       // natural-order input: run of G residues at k = l'*N1 + bitrev(b_lo)*G + jj
       const u32 col = brev(b_lo, log_n1 - log_lines) << log_lines;
-      for (u32 e = t; e < nelem; e += T) {
-        const u32 lp = e >> log_lines, jj = e & (lines - 1);
-        const u64 src = (u64)poly * N + ((u64)lp << log_n1) + col + jj;
-        lds[brev(jj, log_lines) * S::NPAD + pad_idx<LOGL, LOGP>(brev(lp, LOGL))] = ResIO<W>::load(p.src + src);
-      }
+      copy_staged<W, P>(
+          t, T, all,
+          [&](u32 e) {
+            return ResIO<W>::load(p.src + (u64)poly * N + ((u64)(e >> log_lines) << log_n1) + col + (e & (lines - 1)));
+          },
+          [&](u32 e, const Res<W>& v) {
+            lds[brev(e & (lines - 1), log_lines) * S::NPAD + pad_idx<LOGL, LOGP>(brev(e >> log_lines, LOGL))] = v;
+          });
     } else {
-      for (u32 e = t; e < nelem; e += T) {
-        const u32 j = e >> LOGL, l = e & (L - 1);
-        const u32 b = j * n1_over_g + b_lo;
-        lds[j * S::NPAD + pad_idx<LOGL, LOGP>(l)] = ResIO<W>::load(p.src + (u64)poly * N + ((u64)b << LOGL) + l);
-      }
+      copy_staged<W, P>(
+          t, T, all,
+          [&](u32 e) {
+            const u32 b = (e >> LOGL) * n1_over_g + b_lo;
+            return ResIO<W>::load(p.src + (u64)poly * N + ((u64)b << LOGL) + (e & (L - 1)));
+          },
+          [&](u32 e, const Res<W>& v) { lds[(e >> LOGL) * S::NPAD + pad_idx<LOGL, LOGP>(e & (L - 1))] = v; });
     }
   }
   __syncthreads();
@@ -325,35 +354,44 @@ __device__ __forceinline__ void ntt_tile(const NttParams<W>& p, Res<W>* lds, u32
 
   // ---- LDS -> device memory ----
   if (MODE == MODE_FULL) {
-    for (u32 e = t; e < nelem; e += T) {
-      const u32 ln = e >> LOGL, j = e & (L - 1);
-      const u64 pl = (u64)poly * lines + ln;
-      if (pl < p.batch) {
-        const u32 sj = (DIR == DIR_FWD && p.permute) ? brev(j, LOGL) : j;
-        ResIO<W>::store(p.dst + pl * N + j, lds[ln * S::NPAD + pad_idx<LOGL, LOGP>(sj)]);
-      }
-    }
+    copy_staged<W, P>(
+        t, T, [&](u32 e) { return e < nelem && (u64)poly * lines + (e >> LOGL) < p.batch; },
+        [&](u32 e) {
+          const u32 j = e & (L - 1);
+          const u32 sj = (DIR == DIR_FWD && p.permute) ? brev(j, LOGL) : j;
+          return lds[(e >> LOGL) * S::NPAD + pad_idx<LOGL, LOGP>(sj)];
+        },
+        [&](u32 e, const Res<W>& v) {
+          ResIO<W>::store(p.dst + ((u64)poly * lines + (e >> LOGL)) * N + (e & (L - 1)), v);
+        });
   } else if (MODE == MODE_COL) {
     const u64 N2 = (u64)1 << log_n2;
-    for (u32 e = t; e < nelem; e += T) {
-      const u32 r = e >> log_lines, c = e & (lines - 1);
-      ResIO<W>::store(p.dst + (u64)poly * N + r * N2 + c0 + c, lds[c * S::NPAD + pad_idx<LOGL, LOGP>(r)]);
-    }
+    copy_staged<W, P>(
+        t, T, all,
+        [&](u32 e) { return lds[(e & (lines - 1)) * S::NPAD + pad_idx<LOGL, LOGP>(e >> log_lines)]; },
+        [&](u32 e, const Res<W>& v) {
+          ResIO<W>::store(p.dst + (u64)poly * N + (e >> log_lines) * N2 + c0 + (e & (lines - 1)), v);
+        });
   } else {
     const u32 n1_over_g = (1u << log_n1) >> log_lines;
     if (DIR == DIR_FWD && p.permute) {
       const u32 col = brev(b_lo, log_n1 - log_lines) << log_lines;
-      for (u32 e = t; e < nelem; e += T) {
-        const u32 lp = e >> log_lines, jj = e & (lines - 1);
-        const u64 dst = (u64)poly * N + ((u64)lp << log_n1) + col + jj;
-        ResIO<W>::store(p.dst + dst, lds[brev(jj, log_lines) * S::NPAD + pad_idx<LOGL, LOGP>(brev(lp, LOGL))]);
-      }
+      copy_staged<W, P>(
+          t, T, all,
+          [&](u32 e) {
+            return lds[brev(e & (lines - 1), log_lines) * S::NPAD + pad_idx<LOGL, LOGP>(brev(e >> log_lines, LOGL))];
+          },
+          [&](u32 e, const Res<W>& v) {
+            ResIO<W>::store(p.dst + (u64)poly * N + ((u64)(e >> log_lines) << log_n1) + col + (e & (lines - 1)), v);
+          });
     } else {
-      for (u32 e = t; e < nelem; e += T) {
-        const u32 j = e >> LOGL, l = e & (L - 1);
-        const u32 b = j * n1_over_g + b_lo;
-        ResIO<W>::store(p.dst + (u64)poly * N + ((u64)b << LOGL) + l, lds[j * S::NPAD + pad_idx<LOGL, LOGP>(l)]);
-      }
+      copy_staged<W, P>(
+          t, T, all,
+          [&](u32 e) { return lds[(e >> LOGL) * S::NPAD + pad_idx<LOGL, LOGP>(e & (L - 1))]; },
+          [&](u32 e, const Res<W>& v) {
+            const u32 b = (e >> LOGL) * n1_over_g + b_lo;
+            ResIO<W>::store(p.dst + (u64)poly * N + ((u64)b << LOGL) + (e & (L - 1)), v);
+          });
     }
   }
 }
