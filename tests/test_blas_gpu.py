@@ -1,8 +1,8 @@
 """Element-wise modular BLAS on the GPU against the oracle, bit for bit.
 
 Covers both widths (60-bit moduli in one limb, 124-bit in two), lengths that
-are multiples of the kernel's 1024-residue chunk and ragged ones, the paper
-scale length 2^16, every pair of edge residues, exact aliasing (c == a) and
+are multiples of the kernel's chunk and ragged ones, the paper scale length
+2^16, a long ragged vector spanning 1025 blocks (sampled), every pair of edge residues, exact aliasing (c == a) and
 edge scalars for axpy."""
 import itertools
 
@@ -42,6 +42,38 @@ def test_binary_ops(op, n, bits, seed):
     getattr(mwntt, op)(c, a, b, q, limbs)
     torch.cuda.synchronize()
     assert host_ints(c, limbs) == _oracle(op, W.to_ints(A), W.to_ints(B), q)
+
+
+@pytest.mark.parametrize("bits,seed", [(60, 11), (124, 12)])
+def test_long_vector_sampled(bits, seed):
+    """n = 2^20 + 333: 1024 full blocks plus a ragged tail; every 997th
+    element and the whole tail against the oracle."""
+    require_gpu()
+    import torch
+    q = prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    n = (1 << 20) + 333
+    g = W.rng(8080 + bits)
+    A = W.uniform_residues(g, q, n, limbs)
+    B = W.uniform_residues(g, q, n, limbs)
+    alpha = W.uniform_scalar(g, q, limbs)
+    a, b = dev(A), dev(B)
+    ks = list(range(0, n, 997)) + list(range(n - 400, n))
+    sa, sb = W.to_ints(A[ks]), W.to_ints(B[ks])
+
+    def sampled(t):
+        return W.to_ints(mwntt.to_host(t).reshape(-1, limbs)[ks])
+    for op in OPS:
+        announce("long", op, bits)
+        c = torch.empty_like(a)
+        getattr(mwntt, op)(c, a, b, q, limbs)
+        torch.cuda.synchronize()
+        assert sampled(c) == _oracle(op, sa, sb, q), op
+    announce("long axpy", bits)
+    y = b.clone()
+    mwntt.vec_axpymod(y, alpha, a, q, limbs)
+    torch.cuda.synchronize()
+    assert sampled(y) == oracle.modarith.vec_axpymod(alpha, sa, sb, q)
 
 
 @pytest.mark.parametrize("bits,seed", WIDTHS)
