@@ -374,6 +374,34 @@ def main():
     for pl in mplans.values():
         pl.destroy()
 
+    # four-word moduli (252-bit q = 1 mod 2^18): N = 2^16, plain latency,
+    # batch-64 throughput and the BLAS ops, inputs resident in HBM
+    progress("252-bit leg")
+    q8 = W.find_prime(252, 6001)
+    wplan = mwntt.ntt_plan(16, q8, 4)
+    wb = 64
+    wx = mwntt.to_device(W.uniform_residues(W.rng(6100), q8, n * wb, 4))
+    wy, wz = torch.empty_like(wx), torch.empty_like(wx)
+    wplan.forward(wy, wx, batch=wb, stream=sp)
+    wplan.inverse(wz, wy, batch=wb, stream=sp)
+    torch.cuda.synchronize()
+    assert torch.equal(wz, wx), "252-bit round trip failed"
+    w1x, w1y = wx[:n], torch.empty_like(wx[:n])
+    wide = {"q_bits": 252, "N": n,
+            "ntt_forward_us": round(time_calls(lambda: wplan.forward(w1y, w1x, batch=1, stream=sp), stream, reps=50), 2),
+            "ntt_inverse_us": round(time_calls(lambda: wplan.inverse(w1y, w1x, batch=1, stream=sp), stream, reps=50), 2)}
+    wb_us = time_calls(lambda: wplan.forward(wy, wx, batch=wb, stream=sp), stream, reps=10)
+    wide.update({"batch": wb, "batched_us_per_call": round(wb_us, 2), "batched_ntt_s": round(wb / (wb_us * 1e-6), 1),
+                 "batched_gbutterfly_s": round(wb * (n // 2) * log2n / (wb_us * 1e-6) / 1e9, 2)})
+    wa, wbv = wx[:n], wx[n:2 * n]
+    wc = torch.empty_like(wa)
+    for nm, f in (("vec_mulmod_us", lambda: mwntt.vec_mulmod(wc, wa, wbv, q8, 4, stream=sp)),
+                  ("vec_addmod_us", lambda: mwntt.vec_addmod(wc, wa, wbv, q8, 4, stream=sp))):
+        wide[nm] = round(time_calls(f, stream, reps=50), 2)
+    legs["wide_252bit_2e16"] = wide
+    wplan.destroy()
+    del wx, wy, wz
+
     if args.serve_requests:
         progress(f"serving leg: {args.serve_requests} requests")
         legs["serving"] = serving_leg(args.serve_requests)

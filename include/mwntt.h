@@ -12,8 +12,9 @@
  *     Z_q[X]/(X^N + 1), and its inverse (Background, polynomial multiplication
  *     using NTT).
  * Moduli are "double-word" (two 64-bit words, q < 2^124, the largest width the
- * paper's Barrett reduction allows for 128-bit arithmetic) or single-word
- * (q < 2^60, the same rule for one 64-bit word).
+ * paper's Barrett reduction allows for 128-bit arithmetic), single-word
+ * (q < 2^60, the same rule for one 64-bit word) or four-word (q < 2^252: the
+ * larger bit-widths the paper names as the next step, Discussion).
  *
  * Data layout.  A residue is `limbs` little-endian uint64_t words (word 0 is
  * the least significant; the paper's notation [x0, x1] lists the high word
@@ -28,7 +29,8 @@
  * Moduli.  `q` points to `limbs` host words.  limbs == 1: 33 <= bitlen(q) <= 60
  * for vec_mulmod, 2 <= bitlen(q) <= 60 otherwise.  limbs == 2:
  * 97 <= bitlen(q) <= 124 for vec_mulmod, 61 <= bitlen(q) <= 124 otherwise.
- * q must be odd.  Primality is the caller's responsibility (an NTT plan checks
+ * limbs == 4: 225 <= bitlen(q) <= 252 for vec_mulmod, 125 <= bitlen(q) <= 252
+ * otherwise.  Other limb counts are MW_EINVAL.  q must be odd.  Primality is the caller's responsibility (an NTT plan checks
  * that its root has order exactly 2N).
  *
  * Streams and errors.  `stream` is a hipStream_t (NULL = the null stream).
@@ -100,7 +102,9 @@ typedef struct ntt_plan_s* ntt_plan_t;
  * and copies them to device memory, and allocates a scratch buffer for the
  * two-pass transforms.  psi may be NULL (canonical root) or point to `limbs`
  * host words.  flags: 0 or a combination of NTT_BITREV_OUT / NTT_BITREV_IN.
- * Synchronous. */
+ * Argument, modulus and root errors are reported before any device call.
+ * Synchronous (for four-word moduli the host tables take about 1 s at
+ * N = 2^17, mostly the bitwise long divisions of the Shoup companions). */
 int ntt_plan(ntt_plan_t* plan, uint32_t log2n, const uint64_t* q, uint32_t limbs,
              const uint64_t* psi, uint32_t flags);
 /* Frees the plan's device memory (synchronizes the device first). */
@@ -110,7 +114,8 @@ int ntt_plan_root(ntt_plan_t plan, uint64_t* psi_out);
 
 /* Decomposition of the transform (used by the autotuner and by tests):
  * log_n1 == 0 runs each transform in one workgroup (N <= 2^12 for two-word
- * moduli, N <= 2^13 for one-word moduli); otherwise two passes over device
+ * moduli, N <= 2^13 for one-word, N <= 2^11 for four-word moduli); otherwise
+ * two passes over device
  * memory with N1 = 2^log_n1 rows and N2 = N / N1 columns, 3 <= log2(N1),
  * log2(N2) <= 9.  By default a plan holds two measured configurations, one
  * for calls with little work (a single transform spread over as many CUs as
@@ -122,7 +127,8 @@ int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1);
 int ntt_plan_get_split(ntt_plan_t plan, uint32_t* log_n1);
 
 /* Tile shape of one pass (pass 0: single-workgroup transform, 1: column pass,
- * 2: row pass): 2^log_p points per lane (1 <= log_p <= 4) and `lines`
+ * 2: row pass): 2^log_p points per lane (1 <= log_p <= 4; <= 2 for four-word
+ * moduli) and `lines`
  * sub-transforms per workgroup (a power of two; columns per column tile, rows
  * per row tile, transforms per single-workgroup tile).  Rejected (MW_EINVAL)
  * when the pass is not part of the plan's current split or the workgroup would
@@ -150,7 +156,8 @@ int ntt_forward_pass(ntt_plan_t plan, uint32_t pass, void* d_out, const void* d_
 /* Batched executor: many jobs -- forward or inverse transforms, or fused     */
 /* negacyclic products c = INTT(NTT(a) * NTT(b)) (Background, polynomial     */
 /* multiplication using NTT; the schoolbook product reduced mod X^N + 1) --  */
-/* of any mix of lengths (2^6 .. 2^17) and modulus widths, run as one kernel */
+/* of any mix of lengths (2^6 .. 2^17) and one- or two-word modulus widths   */
+/* (four-word plans are rejected with MW_EMODULUS), run as one kernel        */
 /* launch per phase (two for transforms, three when a product is present),   */
 /* each launch covering every job.                                           */
 /* ------------------------------------------------------------------------ */
@@ -219,7 +226,8 @@ enum mw_request_op {
 };
 
 /* One request.  Transform and product requests take q, N and the width from
- * `plan` (N >= 2^6); BLAS requests take q, limbs, n (and alpha for axpy:
+ * `plan` (N >= 2^6; one- or two-word moduli, else MW_EMODULUS); BLAS requests
+ * take q, limbs (1 or 2, else MW_EINVAL), n (and alpha for axpy:
  * out = alpha*in + in2).  `in` / `in2` are device buffers owned by the
  * caller that must stay valid until the request completes; in2 is b for
  * products and BLAS, NULL otherwise. */

@@ -2,7 +2,9 @@
 //
 // A residue of an l-bit modulus is held in W little-endian 32-bit words per
 // lane: W = 2 for q < 2^60 (one 64-bit limb), W = 4 for q < 2^124 (two 64-bit
-// limbs).  The paper's double-word arithmetic (Background, double-word
+// limbs), W = 8 for q < 2^252 (four 64-bit limbs: the wider fields the paper
+// names as the next step beyond 128-bit arithmetic, Discussion, larger
+// bit-widths).  The paper's double-word arithmetic (Background, double-word
 // arithmetic: add with carry, sub with borrow, the schoolbook product of
 // Eq. muls) maps onto CDNA4 vector instructions as follows:
 //   * word product      -> v_mad_u64_u32 (32x32+64 -> 64, with carry-out mask)
@@ -17,9 +19,9 @@
 //   * Shoup multiplication by a constant w with precomputed
 //     w' = floor(w * 2^(32W) / q) (twiddle factors, the axpy scalar).  The
 //     quotient estimate uses only the partial products of columns >= W-1 of
-//     x*w' (columns 0..W-2 are dropped), which under-estimates the exact Shoup
-//     quotient by at most 4 (W=4) or 1 (W=2); the result x*w - Q*q is then in
-//     [0, 6q) for any x < 2^(32W).
+//     x*w' (columns 0..W-2 are dropped; for W = 8 columns >= W-2), which
+//     under-estimates the exact Shoup quotient by at most 4 (W=4) or 1 (W=2,
+//     W=8); the result x*w - Q*q is then in [0, 6q) for any x < 2^(32W).
 //   * Barrett reduction (Background, modular arithmetic, Eq. barrett) for a
 //     product of two variables, with k = 2*bitlen(q): mu = floor(2^(2b)/q),
 //     q1 = floor(x / 2^(b-1)), q3 = floor(q1*mu / 2^(b+1)), r = x - q3*q.
@@ -352,6 +354,112 @@ __device__ __forceinline__ void mul_full(const Res<2>& a, const Res<2>& b, u32 (
 }
 
 // ---------------------------------------------------------------------------
+// Generic W-word products (used for W = 8, four 64-bit limbs).  Product
+// scanning: column c of a*b is the sum of a_i * b_(c-i); a 64-bit accumulator
+// takes the products of a column with their carry-outs counted in t, and the
+// next column starts from {hi(acc), t}.  All loop bounds are compile-time
+// constants, so everything unrolls to straight-line code.
+// ---------------------------------------------------------------------------
+
+// Columns C0..2W-2 of a*b accumulated from column C0 upward (the columns
+// below C0 are not added): out[c - C0] = word c for C0 <= c <= 2W-1.  The
+// truncated sum is below 2^(64W), so nothing carries out of the top word.
+template <int W, int C0>
+__device__ __forceinline__ void mul_cols(const u32 (&a)[W], const u32 (&b)[W], u32 (&out)[2 * W - C0]) {
+  u64 acc = 0;
+  u32 t = 0;
+#pragma unroll
+  for (int c = C0; c <= 2 * W - 2; ++c) {
+    const int i0 = c > W - 1 ? c - (W - 1) : 0;
+    const int i1 = c < W - 1 ? c : W - 1;
+    if (c > C0) acc = pack(hi32(acc), t);
+    t = 0;
+#pragma unroll
+    for (int i = i0; i <= i1; ++i) {
+      if (c == C0 && i == i0) {
+        acc = (u64)a[i] * b[c - i];
+      } else if (c == 2 * W - 2) {
+        acc = mad(a[i], b[c - i], acc);     // top column: the sum fits
+      } else {
+        const u64 cc = mad_cc(a[i], b[c - i], acc);
+        t = add_carry(t, cc);
+      }
+    }
+    out[c - C0] = lo32(acc);
+  }
+  out[2 * W - 1 - C0] = hi32(acc);
+}
+
+// Low W words of a*b (+ c*d when TWO) (columns 0..W-1; column W-2 is only
+// needed modulo 2^64 and column W-1 modulo 2^32).
+template <int W, bool TWO>
+__device__ __forceinline__ void mul_lo_sum(const u32 (&a)[W], const u32 (&b)[W], const u32 (&c)[W],
+                                           const u32 (&d)[W], u32 (&out)[W]) {
+  u64 acc = 0;
+  u32 t = 0;
+#pragma unroll
+  for (int col = 0; col <= W - 3; ++col) {
+    if (col > 0) acc = pack(hi32(acc), t);
+    t = 0;
+#pragma unroll
+    for (int i = 0; i <= col; ++i) {
+      if (col == 0 && i == 0) {
+        acc = (u64)a[0] * b[0];
+      } else {
+        const u64 cc = mad_cc(a[i], b[col - i], acc);
+        t = add_carry(t, cc);
+      }
+    }
+    if constexpr (TWO) {
+#pragma unroll
+      for (int i = 0; i <= col; ++i) {
+        const u64 cc = mad_cc(c[i], d[col - i], acc);
+        t = add_carry(t, cc);
+      }
+    }
+    out[col] = lo32(acc);
+  }
+  acc = pack(hi32(acc), t);
+#pragma unroll
+  for (int i = 0; i <= W - 2; ++i) {
+    acc = mad(a[i], b[W - 2 - i], acc);
+    if constexpr (TWO) acc = mad(c[i], d[W - 2 - i], acc);
+  }
+  out[W - 2] = lo32(acc);
+  u32 top = hi32(acc);
+#pragma unroll
+  for (int i = 0; i <= W - 1; ++i) {
+    top += a[i] * b[W - 1 - i];
+    if constexpr (TWO) top += c[i] * d[W - 1 - i];
+  }
+  out[W - 1] = top;
+}
+
+// Shoup quotient estimate for W = 8: columns >= W-2 of x*ws.  The dropped
+// columns sum to less than 6 * 2^224 * (1 + 2^-32), so the estimate is at
+// most 1 below floor(x*ws / 2^256) and x*w - Q*q lies in [0, 3q).
+__device__ __forceinline__ Res<8> mul_hi_est(const Res<8>& x, const u32 (&ws)[8]) {
+  u32 cols[10];
+  mul_cols<8, 6>(x.v, ws, cols);
+  Res<8> Q;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) Q.v[k] = cols[k + 2];
+  return Q;
+}
+
+__device__ __forceinline__ Res<8> mul_lo2(const Res<8>& x, const u32 (&w)[8], const Res<8>& Q, const u32 (&nq)[8]) {
+  Res<8> r;
+  mul_lo_sum<8, true>(x.v, w, Q.v, nq, r.v);
+  return r;
+}
+
+__device__ __forceinline__ Res<8> mul_lo(const Res<8>& a, const u32 (&b)[8]) {
+  Res<8> r;
+  mul_lo_sum<8, false>(a.v, b, b, b, r.v);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
 // modular multiplication
 // ---------------------------------------------------------------------------
 
@@ -462,6 +570,32 @@ __device__ __forceinline__ Res<2> barrett_mul(const Res<2>& a, const Res<2>& b, 
   return csub(r, M.q);
 }
 
+// Barrett for W = 8 (225 <= bitlen(q) <= 252): the shifts by b - 1 and
+// b + 1 start in word 7; q1*mu drops columns 0..4 (less than 5 * 2^192 *
+// (1 + 2^-32) < 2^(b+1)), so q3 is at most 3 below floor(x/q) and r < 4q.
+__device__ __forceinline__ Res<8> barrett_mul(const Res<8>& a, const Res<8>& b, const Modulus<8>& M) {
+  u32 x[16];
+  mul_cols<8, 0>(a.v, b.v, x);
+  const u32 s1 = (M.bits - 1) & 31;
+  Res<8> q1;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) q1.v[k] = funnel(x[8 + k], x[7 + k], s1);
+  u32 q2[11];   // words 5..15 of the truncated q1*mu
+  mul_cols<8, 5>(q1.v, M.mu, q2);
+  const u32 s3 = (M.bits + 1) & 31;
+  Res<8> q3;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) q3.v[k] = funnel(q2[3 + k], q2[2 + k], s3);   // words 8+k : 7+k
+  Res<8> xl;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) xl.v[k] = x[k];
+  Res<8> qq = mul_lo(q3, M.q);
+  u32 bo;
+  Res<8> r = sub(xl, qq, bo);
+  r = csub(r, M.q2);
+  return csub(r, M.q);
+}
+
 // ---------------------------------------------------------------------------
 // loads / stores of one residue (W words, 16-byte or 8-byte aligned)
 // ---------------------------------------------------------------------------
@@ -488,6 +622,21 @@ template <int W> struct ResIO;
 template <> struct ResIO<4> {
   __device__ static __forceinline__ Res<4> load(const void* p) { return load_res(p); }
   __device__ static __forceinline__ void store(void* p, const Res<4>& r) { store_res(p, r); }
+};
+template <> struct ResIO<8> {
+  __device__ static __forceinline__ Res<8> load(const void* p) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    const uint4 lo = q[0], hi = q[1];
+    Res<8> r;
+    r.v[0] = lo.x; r.v[1] = lo.y; r.v[2] = lo.z; r.v[3] = lo.w;
+    r.v[4] = hi.x; r.v[5] = hi.y; r.v[6] = hi.z; r.v[7] = hi.w;
+    return r;
+  }
+  __device__ static __forceinline__ void store(void* p, const Res<8>& r) {
+    uint4* q = reinterpret_cast<uint4*>(p);
+    q[0] = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+    q[1] = make_uint4(r.v[4], r.v[5], r.v[6], r.v[7]);
+  }
 };
 template <> struct ResIO<2> {
   __device__ static __forceinline__ Res<2> load(const void* p) { return load_res2(p); }

@@ -87,7 +87,7 @@ static int launch_blas(void* d_c, const void* d_a, const void* d_b, size_t n, co
 template <int OP>
 static int blas_dispatch(void* d_c, const void* d_a, const void* d_b, size_t n, const uint64_t* q,
                          uint32_t limbs, const uint64_t* alpha, void* stream) {
-  if (!q || (limbs != 1 && limbs != 2)) return MW_EINVAL;
+  if (!q || (limbs != 1 && limbs != 2 && limbs != 4)) return MW_EINVAL;
   if (n == 0) return MW_OK;
   if (!d_c || !d_a || !d_b) return MW_EINVAL;
   if (n > ((size_t)1 << 40)) return MW_EINVAL;
@@ -95,7 +95,15 @@ static int blas_dispatch(void* d_c, const void* d_a, const void* d_b, size_t n, 
   if (st != MW_OK) return st;
   if (OP == OP_AXPY && !alpha) return MW_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (limbs == 2) {
+  if (limbs == 4) {
+    Modulus<8> M;
+    make_modulus(q, M);
+    Scalar<8> sc = {};
+    if (OP == OP_AXPY) {
+      if (make_scalar(alpha, q, sc.w, sc.ws) != MW_OK) return MW_EINVAL;
+    }
+    return launch_blas<8, OP>(d_c, d_a, d_b, n, M, sc, s);
+  } else if (limbs == 2) {
     Modulus<4> M;
     make_modulus(q, limbs, M);
     Scalar<4> sc = {};

@@ -6,14 +6,24 @@
 #include "../../include/mwntt.h"
 #include "mw_arith.h"
 #include "mw_host_math.h"
+#include "mw_host_wide.h"
 
 namespace mw {
 
-// Width rules (see mwntt.h): limbs == 1 -> q < 2^60, limbs == 2 -> 2^60 <= q < 2^124.
-// Barrett multiplication additionally needs bitlen(q) >= 33 (limbs 1) or
-// >= 97 (limbs 2).
+// Width rules (see mwntt.h): limbs == 1 -> q < 2^60, limbs == 2 ->
+// 2^60 <= q < 2^124, limbs == 4 -> 2^124 <= q < 2^252.  Barrett
+// multiplication additionally needs bitlen(q) >= 33 (limbs 1), >= 97
+// (limbs 2) or >= 225 (limbs 4): its shifts by b - 1 and b + 1 bits then
+// start in the top word of the lower half of a double-width value.
 inline int check_modulus(const uint64_t* q, uint32_t limbs, bool barrett) {
-  if (!q || (limbs != 1 && limbs != 2)) return MW_EINVAL;
+  if (!q || (limbs != 1 && limbs != 2 && limbs != 4)) return MW_EINVAL;
+  if (limbs == 4) {
+    const mwhost::U256 Q = mwhost::u256_from_words(q, 4);
+    const int b = mwhost::bitlen(Q);
+    if (!(Q.w[0] & 1) || b > 252 || b < 125) return MW_EMODULUS;
+    if (barrett && b < 225) return MW_EMODULUS;
+    return MW_OK;
+  }
   mwhost::u128 Q = mwhost::from_words(q, limbs);
   int b = mwhost::bitlen(Q);
   if (!(Q & 1) || Q < 3) return MW_EMODULUS;
@@ -44,6 +54,33 @@ inline void make_modulus(const uint64_t* q, uint32_t limbs, Modulus<W>& M) {
   put_words<W>((mwhost::u128)0 - Q, M.negq);  // 2^(32W) - q (W = 4: 2^128 - q)
   M.bits = (u32)b;
   M.pad_[0] = M.pad_[1] = M.pad_[2] = 0;
+}
+
+template <int W>
+inline void put_words(const mwhost::U256& v, u32 (&out)[W]) {
+  for (int i = 0; i < W; ++i) out[i] = (u32)(v.w[i / 2] >> (32 * (i % 2)));
+}
+
+// Four-word moduli (W = 8 32-bit words).
+inline void make_modulus(const uint64_t* q, Modulus<8>& M) {
+  const mwhost::U256 Q = mwhost::u256_from_words(q, 4);
+  const int b = mwhost::bitlen(Q);
+  put_words<8>(Q, M.q);
+  put_words<8>(mwhost::shl(Q, 1), M.q2);
+  put_words<8>(mwhost::shl(Q, 2), M.q4);
+  put_words<8>(mwhost::shl(Q, 3), M.q8);            // 8q < 2^255
+  put_words<8>(mwhost::pow2_div(2 * b, Q), M.mu);
+  put_words<8>(mwhost::sub(mwhost::u256(0), Q), M.negq);  // 2^256 - q
+  M.bits = (u32)b;
+  M.pad_[0] = M.pad_[1] = M.pad_[2] = 0;
+}
+
+inline int make_scalar(const uint64_t* w, const uint64_t* q, u32 (&wv)[8], u32 (&ws)[8]) {
+  const mwhost::U256 Q = mwhost::u256_from_words(q, 4), Wv = mwhost::u256_from_words(w, 4);
+  if (!(Wv < Q)) return MW_EINVAL;
+  put_words<8>(Wv, wv);
+  put_words<8>(mwhost::shoup(Wv, Q, 256), ws);
+  return MW_OK;
 }
 
 // Constant multiplier and its Shoup companion floor(w * 2^(32W) / q).

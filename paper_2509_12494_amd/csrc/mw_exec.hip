@@ -129,6 +129,7 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
     c4 = {};
     c2 = {};
     if (!plan_view(jb.plan, v, c4.M, c4.ninv, c4.last, c2.M, c2.ninv, c2.last)) return MW_EINVAL;
+    if (v.limbs != 1 && v.limbs != 2) return MW_EMODULUS;   // four-word moduli: plain entry points only
     if (v.log2n < 6) return MW_ESIZE;   // two-pass tiles need N1, N2 >= 8
     if (jb.op == NTT_JOB_POLYMUL && check_modulus(v.q, v.limbs, true) != MW_OK) return MW_EMODULUS;
     JobDesc& d = out.jobs[i];

@@ -18,8 +18,14 @@
 #include "mw_tuned.h"
 
 namespace mw {
-constexpr int kMaxFullLog4 = 12;   // largest single-workgroup transform, two-word moduli
-constexpr int kMaxFullLog2 = 13;   // one-word moduli
+// Largest single-workgroup transform and points-per-lane exponent of a width
+// (limbs 64-bit words per residue; see max_full_log / max_logp).
+inline uint32_t max_full_for(uint32_t limbs) { return (uint32_t)max_full_log(2 * (int)limbs); }
+inline uint32_t max_logp_for(uint32_t limbs) { return (uint32_t)max_logp(2 * (int)limbs); }
+inline size_t tile_lds_for(uint32_t limbs, uint32_t logl, uint32_t logp, uint32_t lines) {
+  return limbs == 4 ? tile_lds_bytes<8>(logl, logp, lines)
+                    : (limbs == 2 ? tile_lds_bytes<4>(logl, logp, lines) : tile_lds_bytes<2>(logl, logp, lines));
+}
 }  // namespace mw
 
 // ---------------------------------------------------------------------------
@@ -45,15 +51,17 @@ struct ntt_plan_s {
   // every call.
   PlanConfig lat, thr;
   bool forced = false;
-  uint64_t q[2] = {0, 0};
-  uint64_t psi[2] = {0, 0};
+  uint64_t q[4] = {0, 0, 0, 0};
+  uint64_t psi[4] = {0, 0, 0, 0};
   int device = 0;
   void* d_tw_fwd = nullptr;   // N entries of {w, w'}
   void* d_tw_inv = nullptr;
   void* d_scratch = nullptr;  // two-pass intermediate
   uint32_t scratch_polys = 0;
+  Modulus<8> M8;
   Modulus<4> M4;
   Modulus<2> M2;
+  Tw<8> ninv8, last8;
   Tw<4> ninv4, last4;
   Tw<2> ninv2, last2;
 };
@@ -65,6 +73,8 @@ void fill_tw(Tw<W>& t, mwhost::u128 w, mwhost::u128 q) {
   put_words<W>(w, t.w);
   put_words<W>(mwhost::shoup(w, q, 32 * W), t.ws);
 }
+
+int upload_tables(ntt_plan_s* P, const void* fwd, const void* inv, size_t bytes);
 
 template <int W>
 int build_tables(ntt_plan_s* P, mwhost::u128 q, mwhost::u128 psi) {
@@ -97,12 +107,44 @@ int build_tables(ntt_plan_s* P, mwhost::u128 q, mwhost::u128 psi) {
     P->ninv2 = tn;
     P->last2 = tl;
   }
-  size_t bytes = sizeof(Tw<W>) * n;
+  return upload_tables(P, fwd.data(), inv.data(), sizeof(Tw<W>) * n);
+}
+
+// Four-word moduli: the same tables from the 256-bit host arithmetic.
+void fill_tw8(Tw<8>& t, const mwhost::U256& w, const mwhost::U256& q) {
+  put_words<8>(w, t.w);
+  put_words<8>(mwhost::shoup(w, q, 256), t.ws);
+}
+
+int upload_tables(ntt_plan_s* P, const void* fwd, const void* inv, size_t bytes) {
   if (hipMalloc(&P->d_tw_fwd, bytes) != hipSuccess) return MW_ENOMEM;
   if (hipMalloc(&P->d_tw_inv, bytes) != hipSuccess) return MW_ENOMEM;
-  if (hipMemcpy(P->d_tw_fwd, fwd.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return MW_EDEVICE;
-  if (hipMemcpy(P->d_tw_inv, inv.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return MW_EDEVICE;
+  if (hipMemcpy(P->d_tw_fwd, fwd, bytes, hipMemcpyHostToDevice) != hipSuccess) return MW_EDEVICE;
+  if (hipMemcpy(P->d_tw_inv, inv, bytes, hipMemcpyHostToDevice) != hipSuccess) return MW_EDEVICE;
   return MW_OK;
+}
+
+int build_tables8(ntt_plan_s* P, const mwhost::Mod256& m, const mwhost::U256& psi) {
+  const uint32_t n = 1u << P->log2n;
+  const int logn = (int)P->log2n;
+  std::vector<Tw<8>> fwd(n), inv(n);
+  const mwhost::U256 psi_inv = mwhost::invmod(psi, m);
+  std::vector<mwhost::U256> pw(n), pwi(n);
+  pw[0] = pwi[0] = mwhost::u256(1);
+  for (uint32_t e = 1; e < n; ++e) {
+    pw[e] = mwhost::mulmod(pw[e - 1], psi, m);
+    pwi[e] = mwhost::mulmod(pwi[e - 1], psi_inv, m);
+  }
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t e = mwhost::bitrev(i, logn);
+    fill_tw8(fwd[i], pw[e], m.q);
+    fill_tw8(inv[i], pwi[e], m.q);
+  }
+  const mwhost::U256 ninv = mwhost::invmod(mwhost::u256(n), m);
+  const mwhost::U256 w1 = (n >= 2) ? pwi[mwhost::bitrev(1, logn)] : mwhost::u256(1);
+  fill_tw8(P->ninv8, ninv, m.q);
+  fill_tw8(P->last8, mwhost::mulmod(w1, ninv, m), m.q);
+  return upload_tables(P, fwd.data(), inv.data(), sizeof(Tw<8>) * n);
 }
 
 void free_plan(ntt_plan_s* P) {
@@ -137,7 +179,11 @@ template <int W>
 int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, int dir, hipStream_t s) {
   NttParams<W> p = {};
   p.tw = reinterpret_cast<const Tw<W>*>(dir == DIR_FWD ? P->d_tw_fwd : P->d_tw_inv);
-  if constexpr (W == 4) {
+  if constexpr (W == 8) {
+    p.M = P->M8;
+    p.ninv = P->ninv8;
+    p.ninv_w1 = P->last8;
+  } else if constexpr (W == 4) {
     p.M = P->M4;
     p.ninv = P->ninv4;
     p.ninv_w1 = P->last4;
@@ -200,14 +246,16 @@ int transform(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, vo
   if (batch == 0) return MW_OK;
   if (!d_out || !d_in) return MW_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return plan->limbs == 2 ? run_transform<4>(plan, d_out, d_in, batch, dir, s)
-                          : run_transform<2>(plan, d_out, d_in, batch, dir, s);
+  switch (plan->limbs) {
+    case 4: return run_transform<8>(plan, d_out, d_in, batch, dir, s);
+    case 2: return run_transform<4>(plan, d_out, d_in, batch, dir, s);
+    default: return run_transform<2>(plan, d_out, d_in, batch, dir, s);
+  }
 }
 
 // Default two-pass split: N1 = 2^floor(log N / 2) rows, N2 = N / N1.
 uint32_t default_split(uint32_t log2n, uint32_t limbs) {
-  const uint32_t max_full = limbs == 2 ? kMaxFullLog4 : kMaxFullLog2;
-  if (log2n <= max_full) return 0;
+  if (log2n <= max_full_for(limbs)) return 0;
   return log2n / 2;
 }
 
@@ -219,39 +267,43 @@ uint32_t thread_bound(uint32_t logl, uint32_t logp) {
 
 // Threads, LDS and shape limits of a tile configuration (see shape_ok).
 bool tile_ok(uint32_t limbs, int mode, uint32_t logl, uint32_t logp, uint32_t lines, uint32_t max_lines) {
-  if (logp < 1 || logp > 4 || logp > logl || logl - logp > 10) return false;
+  if (logp < 1 || logp > max_logp_for(limbs) || logp > logl || logl - logp > 10) return false;
   if (mode == MODE_FULL) {
-    if (logl < 1 || logl > (limbs == 2 ? (uint32_t)kMaxFullLog4 : (uint32_t)kMaxFullLog2)) return false;
+    if (logl < 1 || logl > max_full_for(limbs)) return false;
   } else if (logl < 3 || logl > 9) {
     return false;
   }
   if (lines == 0 || (lines & (lines - 1)) || lines > max_lines) return false;
   if (lines * (1u << (logl - logp)) > thread_bound(logl, logp)) return false;
-  const size_t lds = limbs == 2 ? tile_lds_bytes<4>(logl, logp, lines) : tile_lds_bytes<2>(logl, logp, lines);
-  return lds <= 160 * 1024;
+  return tile_lds_for(limbs, logl, logp, lines) <= 160 * 1024;
 }
 
-// Default tile shapes: 8 points per lane; full tiles fill 256 lanes (or one
-// line); column / row tiles take up to 8 lines (128-byte runs for two-word
-// moduli) within the kernel's thread bound.
-void default_pass(PassCfg& c, uint32_t logl, uint32_t max_lines) {
-  c.logp = logl < 3 ? logl : 3;
+// Default tile shapes: 8 points per lane (4 for four-word moduli); full
+// tiles fill 256 lanes (or one line); column / row tiles take up to 8 lines
+// (128-byte runs for two-word moduli) within the kernel's thread and LDS
+// bounds.
+void default_pass(PassCfg& c, uint32_t limbs, uint32_t logl, uint32_t max_lines) {
+  const uint32_t lp_max = max_logp_for(limbs) < 3 ? max_logp_for(limbs) : 3;
+  c.logp = logl < lp_max ? logl : lp_max;
   const uint32_t tpl = 1u << (logl - c.logp);
   uint32_t lines = 8;
-  while (lines > 1 && (lines * tpl > thread_bound(logl, c.logp) || lines > max_lines)) lines >>= 1;
+  while (lines > 1 && (lines * tpl > thread_bound(logl, c.logp) || lines > max_lines ||
+                       tile_lds_for(limbs, logl, c.logp, lines) > 160 * 1024))
+    lines >>= 1;
   c.lines = lines;
 }
 
-void default_tiles(uint32_t logn, PlanConfig& C) {
-  uint32_t lp = logn < 3 ? logn : 3;
+void default_tiles(uint32_t logn, uint32_t limbs, PlanConfig& C) {
+  const uint32_t lp_max = max_logp_for(limbs) < 3 ? max_logp_for(limbs) : 3;
+  uint32_t lp = logn < lp_max ? logn : lp_max;
   uint32_t tpl = 1u << (logn - lp);
   while (tpl > 1024) { ++lp; tpl >>= 1; }
   C.cfg[MODE_FULL].logp = lp;
   C.cfg[MODE_FULL].lines = tpl >= 256 ? 1 : 256 / tpl;
   if (C.log_n1) {
     const uint32_t l1 = C.log_n1, l2 = logn - C.log_n1;
-    default_pass(C.cfg[MODE_COL], l1, 1u << l2);
-    default_pass(C.cfg[MODE_ROW], l2, 1u << l1);
+    default_pass(C.cfg[MODE_COL], limbs, l1, 1u << l2);
+    default_pass(C.cfg[MODE_ROW], limbs, l2, 1u << l1);
   }
 }
 
@@ -266,7 +318,7 @@ bool config_ok(uint32_t limbs, uint32_t logn, const PlanConfig& C) {
 // an entry for this (width, N).
 void initial_configs(ntt_plan_s* P) {
   P->lat.log_n1 = default_split(P->log2n, P->limbs);
-  default_tiles(P->log2n, P->lat);
+  default_tiles(P->log2n, P->limbs, P->lat);
   P->thr = P->lat;
   for (const TunedCfg& t : kTuned) {
     if (t.limbs != P->limbs || t.log2n != P->log2n) continue;
@@ -319,16 +371,32 @@ bool plan_view(const ntt_plan_s* P, PlanView& v, Modulus<4>& m4, Tw<4>& n4, Tw<4
 }
 }  // namespace mw
 
-extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint32_t limbs,
-                        const uint64_t* psi, uint32_t flags) {
-  if (!out) return MW_EINVAL;
-  *out = nullptr;
-  if (flags & ~(NTT_BITREV_OUT | NTT_BITREV_IN)) return MW_EINVAL;
-  if (log2n < 1 || log2n > 17) return MW_ESIZE;
-  int st = check_modulus(q, limbs, false);
-  if (st != MW_OK) return st;
+namespace {
+// Host-only part of a plan: checks q = 1 (mod 2N), validates or finds the root
+// (written to P->psi) and fills the per-modulus constants.  No device calls,
+// so argument errors are reported without a device.
+int setup_root(ntt_plan_s* P, const uint64_t* q, const uint64_t* psi) {
+  const uint32_t limbs = P->limbs;
+  const uint32_t n = 1u << P->log2n;
+  if (limbs == 4) {
+    const mwhost::U256 Q = mwhost::u256_from_words(q, 4);
+    if (!mwhost::one_mod_2n(Q, P->log2n)) return MW_EMODULUS;
+    const mwhost::Mod256 m = mwhost::mod256(Q);
+    mwhost::U256 root;
+    if (psi) {
+      root = mwhost::u256_from_words(psi, 4);
+      if (mwhost::is_zero(root) || !(root < Q) ||
+          mwhost::powmod(root, mwhost::u256(n), m) != mwhost::sub(Q, mwhost::u256(1)))
+        return MW_EROOT;
+    } else {
+      root = mwhost::canonical_root(m, P->log2n);
+      if (mwhost::is_zero(root)) return MW_EROOT;
+    }
+    mwhost::u256_to_words(root, P->psi, 4);
+    make_modulus(q, P->M8);
+    return MW_OK;
+  }
   mwhost::u128 Q = mwhost::from_words(q, limbs);
-  const uint32_t n = 1u << log2n;
   if ((Q - 1) % (2 * (mwhost::u128)n) != 0) return MW_EMODULUS;
   mwhost::u128 root;
   if (psi) {
@@ -338,21 +406,44 @@ extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint
     root = mwhost::canonical_root(Q, n);
     if (root == 0) return MW_EROOT;
   }
+  mwhost::to_words(root, P->psi, limbs);
+  if (limbs == 2) make_modulus<4>(q, limbs, P->M4);
+  else make_modulus<2>(q, limbs, P->M2);
+  return MW_OK;
+}
+
+// Device part: twiddle tables from P->q and P->psi.
+int setup_tables(ntt_plan_s* P) {
+  if (P->limbs == 4) {
+    const mwhost::U256 Q = mwhost::u256_from_words(P->q, 4);
+    return build_tables8(P, mwhost::mod256(Q), mwhost::u256_from_words(P->psi, 4));
+  }
+  const mwhost::u128 Q = mwhost::from_words(P->q, P->limbs), root = mwhost::from_words(P->psi, P->limbs);
+  return P->limbs == 2 ? build_tables<4>(P, Q, root) : build_tables<2>(P, Q, root);
+}
+}  // namespace
+
+extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint32_t limbs,
+                        const uint64_t* psi, uint32_t flags) {
+  if (!out) return MW_EINVAL;
+  *out = nullptr;
+  if (flags & ~(NTT_BITREV_OUT | NTT_BITREV_IN)) return MW_EINVAL;
+  if (log2n < 1 || log2n > 17) return MW_ESIZE;
+  int st = check_modulus(q, limbs, false);
+  if (st != MW_OK) return st;
   ntt_plan_s* P = new (std::nothrow) ntt_plan_s();
   if (!P) return MW_ENOMEM;
   P->log2n = log2n;
   P->limbs = limbs;
   P->flags = flags;
-  P->q[0] = q[0];
-  P->q[1] = limbs > 1 ? q[1] : 0;
-  mwhost::to_words(root, P->psi, limbs);
-  if (hipGetDevice(&P->device) != hipSuccess) {
+  for (uint32_t i = 0; i < limbs; ++i) P->q[i] = q[i];
+  st = setup_root(P, q, psi);
+  if (st == MW_OK && hipGetDevice(&P->device) != hipSuccess) st = MW_EDEVICE;
+  if (st != MW_OK) {
     delete P;
-    return MW_EDEVICE;
+    return st;
   }
-  if (limbs == 2) make_modulus<4>(q, limbs, P->M4);
-  else make_modulus<2>(q, limbs, P->M2);
-  st = limbs == 2 ? build_tables<4>(P, Q, root) : build_tables<2>(P, Q, root);
+  st = setup_tables(P);
   if (st != MW_OK) {
     free_plan(P);
     return st;
@@ -377,7 +468,9 @@ int run_pass(ntt_plan_s* P, uint32_t pass, void* d_out, const void* d_in, uint32
   if (batch > P->scratch_polys) return MW_ESIZE;
   NttParams<W> p = {};
   p.tw = reinterpret_cast<const Tw<W>*>(P->d_tw_fwd);
-  if constexpr (W == 4) {
+  if constexpr (W == 8) {
+    p.M = P->M8;
+  } else if constexpr (W == 4) {
     p.M = P->M4;
   } else {
     p.M = P->M2;
@@ -410,13 +503,16 @@ extern "C" int ntt_forward_pass(ntt_plan_t plan, uint32_t pass, void* d_out, con
   if (batch == 0) return MW_OK;
   if ((pass == 1 && !d_in) || (pass == 2 && !d_out)) return MW_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return plan->limbs == 2 ? run_pass<4>(plan, pass, d_out, d_in, batch, s)
-                          : run_pass<2>(plan, pass, d_out, d_in, batch, s);
+  switch (plan->limbs) {
+    case 4: return run_pass<8>(plan, pass, d_out, d_in, batch, s);
+    case 2: return run_pass<4>(plan, pass, d_out, d_in, batch, s);
+    default: return run_pass<2>(plan, pass, d_out, d_in, batch, s);
+  }
 }
 
 extern "C" int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1) {
   if (!plan) return MW_EINVAL;
-  const uint32_t max_full = plan->limbs == 2 ? kMaxFullLog4 : kMaxFullLog2;
+  const uint32_t max_full = max_full_for(plan->limbs);
   if (log_n1 == 0) {
     if (plan->log2n > max_full) return MW_ESIZE;
   } else {
@@ -427,7 +523,7 @@ extern "C" int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1) {
   }
   plan->forced = true;
   plan->lat.log_n1 = log_n1;
-  default_tiles(plan->log2n, plan->lat);
+  default_tiles(plan->log2n, plan->limbs, plan->lat);
   plan->thr = plan->lat;
   return MW_OK;
 }
@@ -484,8 +580,7 @@ extern "C" int ntt_plan_destroy(ntt_plan_t plan) {
 
 extern "C" int ntt_plan_root(ntt_plan_t plan, uint64_t* psi_out) {
   if (!plan || !psi_out) return MW_EINVAL;
-  psi_out[0] = plan->psi[0];
-  if (plan->limbs > 1) psi_out[1] = plan->psi[1];
+  for (uint32_t i = 0; i < plan->limbs; ++i) psi_out[i] = plan->psi[i];
   return MW_OK;
 }
 

@@ -55,7 +55,14 @@ struct Tw {
 template <int W>
 __device__ __forceinline__ Tw<W> load_tw(const Tw<W>* t, u32 idx) {
   Tw<W> r;
-  if constexpr (W == 4) {
+  if constexpr (W == 8) {
+    const uint4* p = reinterpret_cast<const uint4*>(t + idx);
+    const uint4 a0 = p[0], a1 = p[1], b0 = p[2], b1 = p[3];
+    r.w[0] = a0.x; r.w[1] = a0.y; r.w[2] = a0.z; r.w[3] = a0.w;
+    r.w[4] = a1.x; r.w[5] = a1.y; r.w[6] = a1.z; r.w[7] = a1.w;
+    r.ws[0] = b0.x; r.ws[1] = b0.y; r.ws[2] = b0.z; r.ws[3] = b0.w;
+    r.ws[4] = b1.x; r.ws[5] = b1.y; r.ws[6] = b1.z; r.ws[7] = b1.w;
+  } else if constexpr (W == 4) {
     const uint4* p = reinterpret_cast<const uint4*>(t + idx);
     uint4 a = p[0], b = p[1];
     r.w[0] = a.x; r.w[1] = a.y; r.w[2] = a.z; r.w[3] = a.w;
@@ -403,14 +410,21 @@ constexpr int max_threads() {
   return tpl > 256 ? (tpl > 1024 ? 1024 : tpl) : 256;
 }
 
+// Largest points-per-lane exponent and single-workgroup transform per width:
+// four-word residues take 8 registers each, so their lanes hold at most 4
+// points, and a single-workgroup transform at most 2^11 of them (LDS).
+__host__ __device__ constexpr int max_logp(int W) { return W == 8 ? 2 : 4; }
+__host__ __device__ constexpr int max_full_log(int W) { return W == 8 ? 11 : (W == 4 ? 12 : 13); }
+
 // Kernel shapes that are instantiated: full transforms of 2^1..2^12 points
-// (2^13 for one-word moduli); column / row lines of 2^3..2^9 points; points per
-// lane 2^1..2^4 with at most 1024 lanes per line.
+// (2^13 for one-word moduli, 2^11 for four-word); column / row lines of
+// 2^3..2^9 points; points per lane 2^1..2^max_logp with at most 1024 lanes
+// per line.
 template <int W, int MODE>
 constexpr bool shape_ok(int logl, int logp) {
-  if (logp < 1 || logp > 4 || logp > logl) return false;
+  if (logp < 1 || logp > max_logp(W) || logp > logl) return false;
   if (logl - logp > 10) return false;
-  if (MODE == MODE_FULL) return logl >= 1 && logl <= (W == 4 ? 12 : 13);
+  if (MODE == MODE_FULL) return logl >= 1 && logl <= max_full_log(W);
   return logl >= 3 && logl <= 9;
 }
 

@@ -320,6 +320,7 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
     Modulus<2> m2;
     Tw<2> a2, b2;
     if (!plan_view(r.plan, v, m4, a4, b4, m2, a2, b2)) return MW_EINVAL;
+    if (v.limbs != 1 && v.limbs != 2) return MW_EMODULUS;   // the executor takes one- and two-word moduli
     if (v.log2n < 6) return MW_ESIZE;
     if (op == MW_REQ_POLYMUL) {
       if (!r.in2) return MW_EINVAL;
@@ -331,6 +332,7 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
     R.cost_us = 1.0 + (double)bytes * v.log2n / 8.0e4;
   } else {
     if (!r.in2 || r.n == 0) return MW_EINVAL;
+    if (r.limbs != 1 && r.limbs != 2) return MW_EINVAL;     // mw_request holds two words of q
     int st = check_modulus(r.q, r.limbs, op == MW_REQ_VEC_MULMOD);
     if (st != MW_OK) return st;
     if (op == MW_REQ_VEC_AXPYMOD) {

@@ -130,10 +130,13 @@ def _check(status: int, where: str) -> None:
         raise MwError(status, where)
 
 
-def _words(x: int, limbs: int):
+def _words(x: int, limbs: int, size: int = 4):
+    """`limbs` little-endian 64-bit words of x in a ctypes array of `size` words."""
+    if limbs > size:
+        raise ValueError(f"at most {size} words here")
     if x < 0 or x >= 1 << (64 * limbs):
         raise ValueError("value does not fit the limb count")
-    arr = (ctypes.c_uint64 * 2)()
+    arr = (ctypes.c_uint64 * size)()
     for i in range(limbs):
         arr[i] = (x >> (64 * i)) & (2**64 - 1)
     return arr
@@ -216,7 +219,7 @@ class NttPlan:
 
     @property
     def root(self) -> int:
-        out = (ctypes.c_uint64 * 2)()
+        out = (ctypes.c_uint64 * 4)()
         _check(lib().ntt_plan_root(self._h, out), "ntt_plan_root")
         return _from_words(out, self.limbs)
 
@@ -332,8 +335,8 @@ def make_request(op: int, inp, inp2=None, plan: Optional[NttPlan] = None, q: int
     r.op = op
     r.plan = plan._h.value if plan is not None else None
     if plan is None:
-        r.q = _words(q, limbs)
-        r.alpha = _words(alpha, limbs)
+        r.q = _words(q, limbs, 2)           # requests carry one- or two-word moduli
+        r.alpha = _words(alpha, limbs, 2)
         r.limbs = limbs
         r.n = n
     r.in_ = _ptr(inp)
@@ -413,19 +416,19 @@ def copy_to_tensor(ptr: int, like, stream=None):
 # host-only helpers
 # ---------------------------------------------------------------------------
 def canonical_root(q: int, limbs: int, log2n: int) -> int:
-    out = (ctypes.c_uint64 * 2)()
+    out = (ctypes.c_uint64 * 4)()
     _check(lib().mw_canonical_root(_words(q, limbs), limbs, log2n, out), "mw_canonical_root")
     return _from_words(out, limbs)
 
 
 def shoup_companion(w: int, q: int, limbs: int) -> int:
-    out = (ctypes.c_uint64 * 2)()
+    out = (ctypes.c_uint64 * 4)()
     _check(lib().mw_shoup_companion(_words(w, limbs), _words(q, limbs), limbs, out), "mw_shoup_companion")
     return _from_words(out, limbs)
 
 
 def barrett_mu(q: int, limbs: int) -> int:
-    out = (ctypes.c_uint64 * 2)()
+    out = (ctypes.c_uint64 * 4)()
     _check(lib().mw_barrett_mu(_words(q, limbs), limbs, out), "mw_barrett_mu")
     return _from_words(out, limbs)
 

@@ -47,7 +47,9 @@ def limbs_for_bits(bits: int) -> int:
         return 1
     if bits <= 124:
         return 2
-    raise ValueError("moduli above 124 bits are not supported")
+    if bits <= 252:
+        return 4
+    raise ValueError("moduli above 252 bits are not supported")
 
 
 def _draw_bits(g: np.random.Generator, nbits: int) -> int:
@@ -75,27 +77,29 @@ def find_prime(bits: int, seed: int, m: int = PRIME_M) -> int:
 def uniform_residues(g: np.random.Generator, q: int, n: int, limbs: int) -> np.ndarray:
     """n residues uniform in [0, q) as a (n, limbs) uint64 array (rejection sampling).
 
-    Each candidate draws ``limbs`` words, masks the top word to the bit length of
-    q minus 64*(limbs-1) bits and is redrawn when >= q (acceptance >= 1/2).
+    Each candidate draws the nw = ceil(bitlen(q) / 64) significant words, masks
+    the top one to the bit length of q minus 64*(nw-1) bits and is redrawn when
+    >= q (acceptance >= 1/2); words above nw are zero.
     """
     bl = q.bit_length()
-    top_bits = bl - 64 * (limbs - 1)
-    if not 1 <= top_bits <= 64:
+    nw = (bl + 63) // 64
+    if not 1 <= nw <= limbs:
         raise ValueError("modulus width does not match the limb count")
+    top_bits = bl - 64 * (nw - 1)
     top_mask = np.uint64((1 << top_bits) - 1) if top_bits < 64 else np.uint64(2**64 - 1)
-    qw = [np.uint64((q >> (64 * i)) & (2**64 - 1)) for i in range(limbs)]
-    out = np.empty((n, limbs), dtype=np.uint64)
+    qw = [np.uint64((q >> (64 * i)) & (2**64 - 1)) for i in range(nw)]
+    out = np.zeros((n, limbs), dtype=np.uint64)
     todo = np.arange(n)
     while todo.size:
-        cand = g.integers(0, 2**64, size=(todo.size, limbs), dtype=np.uint64, endpoint=False)
-        cand[:, limbs - 1] &= top_mask
+        cand = g.integers(0, 2**64, size=(todo.size, nw), dtype=np.uint64, endpoint=False)
+        cand[:, nw - 1] &= top_mask
         # lexicographic compare from the most significant word: cand < q
         less = np.zeros(todo.size, dtype=bool)
         equal = np.ones(todo.size, dtype=bool)
-        for i in range(limbs - 1, -1, -1):
+        for i in range(nw - 1, -1, -1):
             less |= equal & (cand[:, i] < qw[i])
             equal &= cand[:, i] == qw[i]
-        out[todo[less]] = cand[less]
+        out[todo[less], :nw] = cand[less]
         todo = todo[~less]
     return out
 

@@ -34,7 +34,7 @@ SMALL = [(17, [1, 2, 4, 8]), (97, [1, 2, 4, 8, 16]), (193, [2, 4, 8, 16, 32]),
 # search in paper_2509_12494_amd.workloads and checked for primality there.
 def wide_primes():
     from paper_2509_12494_amd import workloads as W
-    return [W.find_prime(60, 7), W.find_prime(124, 8), W.find_prime(124, 2001)]
+    return [W.find_prime(60, 7), W.find_prime(124, 8), W.find_prime(124, 2001), W.find_prime(252, 9)]
 
 
 def _poly_eval(coeffs, x, q):

@@ -228,3 +228,9 @@ def test_batch_argument_errors():
     y = torch.zeros(256, 1, dtype=torch.int64, device="cuda")
     with pytest.raises(mwntt.MwError):
         mwntt.NttBatch([(p60, mwntt.NTT_JOB_POLYMUL, y, None, y)])   # product without b
+    p252 = mwntt.ntt_plan(8, prime(252, 41), 4)   # four-word moduli: plain entry points only
+    z = torch.zeros(256, 4, dtype=torch.int64, device="cuda")
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.NttBatch([(p252, mwntt.NTT_JOB_FORWARD, z, None, z)])
+    assert e.value.status == -2
+    p252.destroy()

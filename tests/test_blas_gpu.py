@@ -1,6 +1,7 @@
 """Element-wise modular BLAS on the GPU against the oracle, bit for bit.
 
-Covers both widths (60-bit moduli in one limb, 124-bit in two), lengths that
+Covers the three widths (60-bit moduli in one limb, 124-bit in two, 225- and
+252-bit in four), lengths that
 are multiples of the kernel's chunk and ragged ones, the paper scale length
 2^16, a long ragged vector spanning 1025 blocks (sampled), every pair of edge residues, exact aliasing (c == a) and
 edge scalars for axpy."""
@@ -16,7 +17,7 @@ from .gpu_util import announce, dev, edge_values, host_ints, prime, require_gpu
 
 pytestmark = pytest.mark.gpu
 
-WIDTHS = [(60, 11), (124, 12), (124, 2001), (97, 13), (33, 14)]
+WIDTHS = [(60, 11), (124, 12), (124, 2001), (97, 13), (33, 14), (252, 15), (225, 16)]
 SIZES = [1, 7, 1024, 1024 + 37, 3 * 4096 + 5, 1 << 16]
 OPS = ["vec_addmod", "vec_submod", "vec_mulmod"]
 
@@ -44,7 +45,7 @@ def test_binary_ops(op, n, bits, seed):
     assert host_ints(c, limbs) == _oracle(op, W.to_ints(A), W.to_ints(B), q)
 
 
-@pytest.mark.parametrize("bits,seed", [(60, 11), (124, 12)])
+@pytest.mark.parametrize("bits,seed", [(60, 11), (124, 12), (252, 15)])
 def test_long_vector_sampled(bits, seed):
     """n = 2^20 + 333: 1024 full blocks plus a ragged tail; every 997th
     element and the whole tail against the oracle."""
@@ -119,7 +120,7 @@ def test_edge_pairs(bits, seed):
         assert host_ints(y, limbs) == oracle.modarith.vec_axpymod(alpha, a_i, b_i, q)
 
 
-@pytest.mark.parametrize("bits,seed", [(60, 11), (124, 12)])
+@pytest.mark.parametrize("bits,seed", [(60, 11), (124, 12), (252, 15)])
 def test_in_place_aliasing(bits, seed):
     require_gpu()
     import torch

@@ -39,7 +39,8 @@ def test_status_strings():
     assert mwntt.version().startswith("mwntt")
 
 
-@pytest.mark.parametrize("bits,seed", [(60, 1), (60, 3001), (124, 1001), (124, 2001), (124, 4001)])
+@pytest.mark.parametrize("bits,seed", [(60, 1), (60, 3001), (124, 1001), (124, 2001), (124, 4001),
+                                       (252, 6001), (225, 6002), (160, 6003)])
 def test_canonical_root_matches_oracle(bits, seed):
     q = W.find_prime(bits, seed)
     limbs = W.limbs_for_bits(bits)
@@ -54,7 +55,7 @@ def test_canonical_root_small_primes():
         assert mwntt.canonical_root(q, 1, log2n) == oracle.roots.canonical_psi(q, n)
 
 
-@pytest.mark.parametrize("bits", [60, 124])
+@pytest.mark.parametrize("bits", [60, 124, 252, 225, 130])
 def test_shoup_and_barrett_constants(bits):
     q = W.find_prime(bits, 77)
     limbs = W.limbs_for_bits(bits)
@@ -105,6 +106,20 @@ def test_argument_errors_without_device():
     assert e.value.status == -2
     with pytest.raises(mwntt.MwError) as e:
         mwntt.vec_axpymod(8, q60, 8, q60, 1, n=5, stream=0)  # alpha not reduced
+    assert e.value.status == -1
+    # four-word moduli: 125..252 bits, Barrett from 225 bits
+    q200 = W.find_prime(200, 6004)
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.vec_mulmod(8, 8, 8, q200, 4, n=5, stream=0)
+    assert e.value.status == -2
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.ntt_plan(10, q124, 4)                 # 124-bit q in four limbs
+    assert e.value.status == -2
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.vec_addmod(8, 8, 8, (1 << 253) + 1, 4, n=5, stream=0)   # above 252 bits
+    assert e.value.status == -2
+    with pytest.raises(mwntt.MwError) as e:
+        mwntt.vec_addmod(8, 8, 8, q60, 3, n=5, stream=0)              # three limbs
     assert e.value.status == -1
 
 

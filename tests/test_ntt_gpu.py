@@ -1,6 +1,7 @@
 """Negacyclic NTT / INTT on the GPU against the oracle, bit for bit.
 
-* every single-workgroup size 2^1 .. 2^10, both widths, whole outputs against
+* every single-workgroup size 2^1 .. 2^10, all three widths (60, 124, 252
+  bits), whole outputs against
   the oracle's definition (O(N^2));
 * the two-pass path forced at small N over several splits (several column and
   row tiles), whole outputs against the oracle;
@@ -23,7 +24,7 @@ from .gpu_util import announce, bitrev, dev, host_ints, prime, require_gpu
 
 pytestmark = pytest.mark.gpu
 
-WIDTHS = [(60, 21), (124, 22)]
+WIDTHS = [(60, 21), (124, 22), (252, 23)]
 
 
 @functools.lru_cache(maxsize=None)

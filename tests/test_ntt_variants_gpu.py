@@ -53,7 +53,7 @@ def _check(plan, A, want, limbs, tag):
     assert torch.equal(z, x), tag
 
 
-@pytest.mark.parametrize("bits", [60, 124])
+@pytest.mark.parametrize("bits", [60, 124, 252])
 @pytest.mark.parametrize("log2n", [5, 8, 10])
 def test_full_tile_shapes(log2n, bits):
     require_gpu()
@@ -68,7 +68,7 @@ def test_full_tile_shapes(log2n, bits):
     plan.destroy()
 
 
-@pytest.mark.parametrize("bits", [60, 124])
+@pytest.mark.parametrize("bits", [60, 124, 252])
 @pytest.mark.parametrize("log2n,log_n1", [(8, 4), (10, 3), (10, 5), (10, 7), (11, 5)])
 def test_two_pass_shapes(log2n, log_n1, bits):
     require_gpu()
