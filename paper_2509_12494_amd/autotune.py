@@ -47,7 +47,7 @@ def _valid_shapes(plan, pass_):
 
 
 def _splits(log2n, limbs):
-    max_full = 12 if limbs == 2 else 13
+    max_full = {1: 13, 2: 12, 4: 11}[limbs]
     s = [0] if log2n <= max_full else []
     s += [l1 for l1 in range(3, 10) if 3 <= log2n - l1 <= 9]
     return s
@@ -130,7 +130,7 @@ def emit_header(jsonl_paths, out_path: str) -> None:
     for path in jsonl_paths:
         for line in open(path):
             r = json.loads(line)
-            key = (2 if r["bits"] > 60 else 1, r["log2n"])
+            key = (W.limbs_for_bits(r["bits"]), r["log2n"])
             kind = 0 if r["batch"] == 1 else 1
             cur = best.get((key, kind))
             if kind == 1 and cur is not None and cur[0] > r["batch"]:
