@@ -100,7 +100,8 @@ typedef struct ntt_plan_s* ntt_plan_t;
 /* Creates a plan on the current HIP device: builds the twiddle tables
  * (psi^bitrev(i) and psi^-bitrev(i) with their Shoup companions) on the host
  * and copies them to device memory, and allocates a scratch buffer for the
- * two-pass transforms.  psi may be NULL (canonical root) or point to `limbs`
+ * two-pass transforms (256 polynomials, within 64 .. 256 MiB; larger batches
+ * run in chunks of that many).  psi may be NULL (canonical root) or point to `limbs`
  * host words.  flags: 0 or a combination of NTT_BITREV_OUT / NTT_BITREV_IN.
  * Argument, modulus and root errors are reported before any device call.
  * Synchronous (for four-word moduli the host tables take about 1 s at

@@ -91,7 +91,7 @@ __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J,
   }
 }
 
-__global__ __launch_bounds__(kExecThreads) void exec_kernel(ExecParams ep) {
+__global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(4))) void exec_kernel(ExecParams ep) {
   extern __shared__ __align__(16) unsigned char mw_exec_smem[];
   const uint2 it = ep.items[blockIdx.x];
   const u32 job = it.x, phase = it.y >> 16, tile = it.y & 0xffffu;

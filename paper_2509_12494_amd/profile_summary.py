@@ -7,8 +7,9 @@
 `kernels` lists every kernel (grouped by name and grid size) with its launch
 count and average / min / max duration.  `counters` reads FETCH_SIZE and
 WRITE_SIZE (KiB per dispatch) from two separate counter runs and converts them
-to bytes with the factor that makes the largest device-to-device copy kernel
-of the run (`__amd_rocclr_copyBuffer`, BYTES long) read and write exactly BYTES.
+to bytes with the factor that makes the largest single device-to-device copy
+dispatch of the run (`__amd_rocclr_copyBuffer`, BYTES long) read and write
+exactly BYTES.
 """
 import argparse
 import sqlite3
@@ -39,16 +40,22 @@ def _counter(db, counter):
     return [(k, g // max(w, 1), v * 1024.0, n) for k, g, w, v, n in con.execute(q, (counter,))]
 
 
+def _largest_copy(db, counter):
+    """Counter value (bytes) of the single largest device copy dispatch: the
+    calibration copy of known size (other copies of the run are smaller)."""
+    con = sqlite3.connect(db)
+    q = ("select max(value) from counters_collection "
+         "where counter_name = ? and kernel_name like '%copyBuffer%'")
+    (v,), = con.execute(q, (counter,))
+    return v * 1024.0
+
+
 def counters(fetch_db, write_db, copy_bytes, match=None):
     fetch = _counter(fetch_db, "FETCH_SIZE")
     write = _counter(write_db, "WRITE_SIZE")
-
-    def scale(rows):
-        copies = [r for r in rows if "copyBuffer" in r[0]]
-        big = max(copies, key=lambda r: r[2])
-        return copy_bytes / big[2], big[2]
-    fs, fraw = scale(fetch)
-    ws, wraw = scale(write)
+    fraw = _largest_copy(fetch_db, "FETCH_SIZE")
+    wraw = _largest_copy(write_db, "WRITE_SIZE")
+    fs, ws = copy_bytes / fraw, copy_bytes / wraw
     wmap = {(k, g): v for k, g, v, _ in write}
     out = []
     for k, g, v, n in fetch:

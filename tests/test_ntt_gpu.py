@@ -136,14 +136,16 @@ def test_default_config_sampled(log2n, bits, seed):
 
 @pytest.mark.parametrize("bits,seed", WIDTHS)
 def test_batch_beyond_scratch_chunk(bits, seed):
-    """2^17-point transforms, more polynomials than one 64 MiB scratch chunk."""
+    """2^17-point transforms, more polynomials than one scratch chunk (the
+    plan's scratch holds 256 polynomials within [64 MiB, 256 MiB])."""
     require_gpu()
     import torch
     log2n = 17
     q = prime(bits, seed)
     limbs = W.limbs_for_bits(bits)
     n = 1 << log2n
-    per_chunk = (64 << 20) // (8 * limbs * n)
+    poly_bytes = 8 * limbs * n
+    per_chunk = min(max(256 * poly_bytes, 64 << 20), 256 << 20) // poly_bytes
     batch = per_chunk + 3
     A = W.uniform_residues(W.rng(5), q, n * batch, limbs)
     announce("chunked batch", batch, bits)
