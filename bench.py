@@ -188,7 +188,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=96, help="transforms per call in the batched leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=40000,
+    ap.add_argument("--serve-requests", type=int, default=100000,
                     help="requests in the serving leg (Poisson, 20k requests/s); 0 skips it")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
@@ -243,6 +243,7 @@ def main():
     ev0.record(stream)
     for _ in range(args.steps):
         step()
+    t_enq = time.perf_counter() - t0       # host time to issue the K steps
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -374,6 +375,30 @@ def main():
     for pl in mplans.values():
         pl.destroy()
 
+    # RNS form (the FHE shape): polynomials mod Q = q_1 ... q_8, eight 124-bit
+    # primes sharing N = 2^16; 4 RNS products = 32 fused product jobs in one
+    # executor run (hipGraph replay)
+    progress("rns leg")
+    rqs = W.config_rns()
+    rplans = [mwntt.ntt_plan(16, rq, 2) for rq in rqs]
+    rpolys = 4
+    rjobs = []
+    for j in range(rpolys):
+        for i, rq in enumerate(rqs):
+            ra = mwntt.to_device(W.uniform_residues(W.rng(7200 + 16 * j + i), rq, n, 2))
+            rb = mwntt.to_device(W.uniform_residues(W.rng(7300 + 16 * j + i), rq, n, 2))
+            rjobs.append((rplans[i], mwntt.NTT_JOB_POLYMUL, ra, rb, torch.empty_like(ra)))
+    rbatch = mwntt.NttBatch(rjobs)
+    rns_us = time_graph(lambda s_: rbatch.run(stream=s_), stream)
+    legs["rns_8x124bit_2e16"] = {"moduli": len(rqs), "q_bits": 124, "N": n, "rns_products": rpolys,
+                                 "us_per_run": round(rns_us, 2),
+                                 "rns_products_s": round(rpolys / (rns_us * 1e-6), 1),
+                                 "residue_products_s": round(len(rjobs) / (rns_us * 1e-6), 1)}
+    rbatch.destroy()
+    for pl in rplans:
+        pl.destroy()
+    del rjobs
+
     # four-word moduli (252-bit q = 1 mod 2^18): N = 2^16, plain latency,
     # batch-64 throughput and the BLAS ops, inputs resident in HBM
     progress("252-bit leg")
@@ -466,6 +491,10 @@ def main():
                      "hbm_gbs_algorithmic": round(d["bytes"] / (d["us"] * 1e-6) / 1e9, 1),
                      "passes_us": {str(k): round(v["us"], 3) for k, v in passes.items()}},
         "wall_s_timed_region": round(wall, 4),
+        # host time to issue one step (7 library calls through the Python
+        # binding); close to ms_per_step means the plain step is bound by
+        # call submission rather than by the GPU
+        "host_issue_us_per_step": round(t_enq / args.steps * 1e6, 2),
     }
     if args.copy_calibration_mib:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale

@@ -84,6 +84,59 @@ static int launch_blas(void* d_c, const void* d_a, const void* d_b, size_t n, co
   return hipGetLastError() == hipSuccess ? MW_OK : MW_EDEVICE;
 }
 
+// Per-thread memo of the last modulus (and axpy scalar) of each width: the
+// constants (Barrett mu and the Shoup companion come from bitwise long
+// division) are the same on every call of a loop over one modulus.
+template <int W>
+struct ModMemo {
+  uint64_t q[4] = {0, 0, 0, 0};
+  Modulus<W> M{};
+  bool valid = false;
+  uint64_t alpha[4] = {0, 0, 0, 0};
+  Scalar<W> sc{};
+  bool sc_valid = false;
+};
+
+static bool same_words(const uint64_t* a, const uint64_t* b, uint32_t limbs) {
+  for (uint32_t i = 0; i < limbs; ++i)
+    if (a[i] != b[i]) return false;
+  return true;
+}
+
+template <int W>
+static const Modulus<W>& memo_modulus(const uint64_t* q, uint32_t limbs) {
+  thread_local ModMemo<W> m;
+  if (!m.valid || !same_words(m.q, q, limbs)) {
+    if constexpr (W == 8) make_modulus(q, m.M);
+    else make_modulus<W>(q, limbs, m.M);
+    for (uint32_t i = 0; i < 4; ++i) m.q[i] = i < limbs ? q[i] : 0;
+    m.valid = true;
+    m.sc_valid = false;
+  }
+  return m.M;
+}
+
+// alpha and its Shoup companion, memoized per thread by (q, alpha)
+template <int W>
+static int memo_scalar(const uint64_t* alpha, const uint64_t* q, uint32_t limbs, Scalar<W>& out) {
+  thread_local ModMemo<W> m;   // separate memo: keyed by (q, alpha)
+  if (!m.sc_valid || !same_words(m.q, q, limbs) || !same_words(m.alpha, alpha, limbs)) {
+    Scalar<W> sc = {};
+    int st;
+    if constexpr (W == 8) st = make_scalar(alpha, q, sc.w, sc.ws);
+    else st = make_scalar(alpha, q, limbs, sc.w, sc.ws);
+    if (st != MW_OK) return st;
+    for (uint32_t i = 0; i < 4; ++i) {
+      m.q[i] = i < limbs ? q[i] : 0;
+      m.alpha[i] = i < limbs ? alpha[i] : 0;
+    }
+    m.sc = sc;
+    m.sc_valid = true;
+  }
+  out = m.sc;
+  return MW_OK;
+}
+
 template <int OP>
 static int blas_dispatch(void* d_c, const void* d_a, const void* d_b, size_t n, const uint64_t* q,
                          uint32_t limbs, const uint64_t* alpha, void* stream) {
@@ -96,29 +149,17 @@ static int blas_dispatch(void* d_c, const void* d_a, const void* d_b, size_t n, 
   if (OP == OP_AXPY && !alpha) return MW_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (limbs == 4) {
-    Modulus<8> M;
-    make_modulus(q, M);
     Scalar<8> sc = {};
-    if (OP == OP_AXPY) {
-      if (make_scalar(alpha, q, sc.w, sc.ws) != MW_OK) return MW_EINVAL;
-    }
-    return launch_blas<8, OP>(d_c, d_a, d_b, n, M, sc, s);
+    if (OP == OP_AXPY && memo_scalar<8>(alpha, q, limbs, sc) != MW_OK) return MW_EINVAL;
+    return launch_blas<8, OP>(d_c, d_a, d_b, n, memo_modulus<8>(q, limbs), sc, s);
   } else if (limbs == 2) {
-    Modulus<4> M;
-    make_modulus(q, limbs, M);
     Scalar<4> sc = {};
-    if (OP == OP_AXPY) {
-      if (make_scalar(alpha, q, limbs, sc.w, sc.ws) != MW_OK) return MW_EINVAL;
-    }
-    return launch_blas<4, OP>(d_c, d_a, d_b, n, M, sc, s);
+    if (OP == OP_AXPY && memo_scalar<4>(alpha, q, limbs, sc) != MW_OK) return MW_EINVAL;
+    return launch_blas<4, OP>(d_c, d_a, d_b, n, memo_modulus<4>(q, limbs), sc, s);
   } else {
-    Modulus<2> M;
-    make_modulus(q, limbs, M);
     Scalar<2> sc = {};
-    if (OP == OP_AXPY) {
-      if (make_scalar(alpha, q, limbs, sc.w, sc.ws) != MW_OK) return MW_EINVAL;
-    }
-    return launch_blas<2, OP>(d_c, d_a, d_b, n, M, sc, s);
+    if (OP == OP_AXPY && memo_scalar<2>(alpha, q, limbs, sc) != MW_OK) return MW_EINVAL;
+    return launch_blas<2, OP>(d_c, d_a, d_b, n, memo_modulus<2>(q, limbs), sc, s);
   }
 }
 

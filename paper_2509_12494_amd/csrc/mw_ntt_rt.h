@@ -27,10 +27,12 @@ __device__ __forceinline__ u32 rt_npad(u32 logl, u32 logp) {
 }
 
 // One round of NP stages (NP <= LOGP) starting at stage s0 of the line.
-template <int W, int LOGP, int NP, int DIR>
+// LAST_INV: the round may hold the final inverse stage (stage 0, N^-1 folded
+// in); CANON: make the outputs canonical.  Both are known where a round is
+// called, so rounds without them carry no code for them.
+template <int W, int LOGP, int NP, int DIR, bool LAST_INV, bool CANON>
 __device__ __forceinline__ void rt_round(Res<W>* line, bool active, u32 logl, u32 s0, u32 tid, u32 base,
-                                         const Tw<W>* __restrict__ tw, const NttParams<W>& p, bool last_inv,
-                                         bool canon) {
+                                         const Tw<W>* __restrict__ tw, const NttParams<W>& p) {
   constexpr int P = 1 << LOGP;
   if (active) {
     const u32 L0 = logl - s0 - LOGP;
@@ -48,7 +50,7 @@ __device__ __forceinline__ void rt_round(Res<W>* line, bool active, u32 logl, u3
       for (int gi = 0; gi < ngroups; ++gi) {
         const u32 j0 = base_j | ((u32)(gi << (ib + 1)) << L0);
         const u32 g = j0 >> (logl - s);
-        if (DIR == DIR_INV && s == 0 && last_inv) {
+        if (DIR == DIR_INV && LAST_INV && s == 0) {
 #pragma unroll
           for (int lo = 0; lo < (1 << ib); ++lo) {
             const int u = (gi << (ib + 1)) | lo;
@@ -65,7 +67,7 @@ __device__ __forceinline__ void rt_round(Res<W>* line, bool active, u32 logl, u3
         }
       }
     }
-    if (canon) {
+    if constexpr (CANON) {
 #pragma unroll
       for (int u = 0; u < P; ++u) x[u] = canon16(x[u], p.M);
     }
@@ -75,41 +77,46 @@ __device__ __forceinline__ void rt_round(Res<W>* line, bool active, u32 logl, u3
   __syncthreads();
 }
 
-template <int W, int LOGP, int DIR>
+template <int W, int LOGP, int DIR, bool LAST_INV, bool CANON>
 __device__ __forceinline__ void rt_first_round(u32 p0, Res<W>* line, bool active, u32 logl, u32 tid, u32 base,
-                                               const Tw<W>* __restrict__ tw, const NttParams<W>& p,
-                                               bool last_inv, bool canon) {
+                                               const Tw<W>* __restrict__ tw, const NttParams<W>& p) {
   // p0 in [1, LOGP]: stages 0 .. p0-1 of the line
   if constexpr (LOGP >= 1) {
-    if (p0 == 1) { rt_round<W, LOGP, 1, DIR>(line, active, logl, 0, tid, base, tw, p, last_inv, canon); return; }
+    if (p0 == 1) { rt_round<W, LOGP, 1, DIR, LAST_INV, CANON>(line, active, logl, 0, tid, base, tw, p); return; }
   }
   if constexpr (LOGP >= 2) {
-    if (p0 == 2) { rt_round<W, LOGP, 2, DIR>(line, active, logl, 0, tid, base, tw, p, last_inv, canon); return; }
+    if (p0 == 2) { rt_round<W, LOGP, 2, DIR, LAST_INV, CANON>(line, active, logl, 0, tid, base, tw, p); return; }
   }
   if constexpr (LOGP >= 3) {
-    if (p0 == 3) { rt_round<W, LOGP, 3, DIR>(line, active, logl, 0, tid, base, tw, p, last_inv, canon); return; }
+    if (p0 == 3) { rt_round<W, LOGP, 3, DIR, LAST_INV, CANON>(line, active, logl, 0, tid, base, tw, p); return; }
   }
   if constexpr (LOGP >= 4) {
-    rt_round<W, LOGP, 4, DIR>(line, active, logl, 0, tid, base, tw, p, last_inv, canon);
+    rt_round<W, LOGP, 4, DIR, LAST_INV, CANON>(line, active, logl, 0, tid, base, tw, p);
   }
 }
 
 // All stages of a line of 2^logl points (logl >= LOGP) held in LDS.
-template <int W, int LOGP, int DIR>
+// LAST_INV: the line holds the final inverse stage; FINAL_FWD: canonicalize
+// after the last forward stage.
+template <int W, int LOGP, int DIR, bool LAST_INV, bool FINAL_FWD>
 __device__ __forceinline__ void rt_line_stages(Res<W>* line, bool active, u32 logl, u32 tid, u32 base,
-                                               const Tw<W>* __restrict__ tw, const NttParams<W>& p, bool last_inv,
-                                               bool final_fwd) {
+                                               const Tw<W>* __restrict__ tw, const NttParams<W>& p) {
   const u32 R = (logl + LOGP - 1) / LOGP;
   const u32 p0 = logl - LOGP * (R - 1);
   if (DIR == DIR_FWD) {
-    rt_first_round<W, LOGP, DIR>(p0, line, active, logl, tid, base, tw, p, last_inv, final_fwd && R == 1);
-    for (u32 r = 1; r < R; ++r)
-      rt_round<W, LOGP, LOGP, DIR>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p, last_inv,
-                                   final_fwd && r == R - 1);
+    if (R == 1) {
+      rt_first_round<W, LOGP, DIR, false, FINAL_FWD>(p0, line, active, logl, tid, base, tw, p);
+      return;
+    }
+    rt_first_round<W, LOGP, DIR, false, false>(p0, line, active, logl, tid, base, tw, p);
+    for (u32 r = 1; r + 1 < R; ++r)
+      rt_round<W, LOGP, LOGP, DIR, false, false>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p);
+    rt_round<W, LOGP, LOGP, DIR, false, FINAL_FWD>(line, active, logl, p0 + (R - 2) * LOGP, tid, base, tw, p);
   } else {
+    // only the first round holds stage 0
     for (u32 r = R - 1; r >= 1; --r)
-      rt_round<W, LOGP, LOGP, DIR>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p, last_inv, false);
-    rt_first_round<W, LOGP, DIR>(p0, line, active, logl, tid, base, tw, p, last_inv, false);
+      rt_round<W, LOGP, LOGP, DIR, false, false>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p);
+    rt_first_round<W, LOGP, DIR, LAST_INV, false>(p0, line, active, logl, tid, base, tw, p);
   }
 }
 
@@ -170,9 +177,8 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
 
   u32 base = 1;
   if (MODE == MODE_ROW) base = (1u << log_n1) + line_id * ((1u << log_n1) >> log_lines) + b_lo;
-  const bool last_inv = (DIR == DIR_INV) && (MODE == MODE_COL);
-  const bool final_fwd = (DIR == DIR_FWD) && (MODE == MODE_ROW);
-  rt_line_stages<W, LOGP, DIR>(lds + line_id * npad, active, logl, lane, base, p.tw, p, last_inv, final_fwd);
+  rt_line_stages<W, LOGP, DIR, DIR == DIR_INV && MODE != MODE_ROW, DIR == DIR_FWD && MODE != MODE_COL>(
+      lds + line_id * npad, active, logl, lane, base, p.tw, p);
 
   // ---- LDS -> device memory ----
   if (MODE == MODE_COL) {
@@ -256,15 +262,15 @@ __device__ __forceinline__ void rt_fused_row(const NttParams<W>& pf, const NttPa
   }
   __syncthreads();
   const u32 base = (1u << log_n1) + row0 + line_id;
-  rt_line_stages<W, LOGP, DIR_FWD>(la + line_id * npad, active, logl, lane, base, pf.tw, pf, false, true);
-  rt_line_stages<W, LOGP, DIR_FWD>(lb + line_id * npad, active, logl, lane, base, pf.tw, pf, false, true);
+  rt_line_stages<W, LOGP, DIR_FWD, false, true>(la + line_id * npad, active, logl, lane, base, pf.tw, pf);
+  rt_line_stages<W, LOGP, DIR_FWD, false, true>(lb + line_id * npad, active, logl, lane, base, pf.tw, pf);
   for (u32 e = t; e < nelem; e += nthreads) {
     const u32 j = e >> logl, l = e & (L - 1);
     const u32 idx = j * npad + rt_pad<LOGP>(l, logl);
     la[idx] = barrett_mul(la[idx], lb[idx], pf.M);
   }
   __syncthreads();
-  rt_line_stages<W, LOGP, DIR_INV>(la + line_id * npad, active, logl, lane, base, pi.tw, pi, false, false);
+  rt_line_stages<W, LOGP, DIR_INV, false, false>(la + line_id * npad, active, logl, lane, base, pi.tw, pi);
   copy_staged<W, P>(
       t, nthreads, in_tile, [&](u32 e) { return la[slot(e)]; },
       [&](u32 e, const Res<W>& v) { ResIO<W>::store(pf.dst + off(e), v); });

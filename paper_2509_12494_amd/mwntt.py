@@ -12,6 +12,7 @@ torch's current stream.
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 from typing import Optional
 
@@ -130,8 +131,12 @@ def _check(status: int, where: str) -> None:
         raise MwError(status, where)
 
 
+@functools.lru_cache(maxsize=1024)
 def _words(x: int, limbs: int, size: int = 4):
-    """`limbs` little-endian 64-bit words of x in a ctypes array of `size` words."""
+    """`limbs` little-endian 64-bit words of x in a ctypes array of `size` words.
+
+    Cached: the arrays are read-only inputs of the C calls (moduli, roots and
+    scalars recur on every call), so they are built once per value."""
     if limbs > size:
         raise ValueError(f"at most {size} words here")
     if x < 0 or x >= 1 << (64 * limbs):

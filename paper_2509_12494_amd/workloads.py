@@ -104,6 +104,13 @@ def uniform_residues(g: np.random.Generator, q: int, n: int, limbs: int) -> np.n
     return out
 
 
+def uniform_ints(g: np.random.Generator, q: int, n: int) -> List[int]:
+    """n Python ints uniform in [0, q) for a modulus of any width (rejection on
+    ceil(bitlen(q)/64) drawn words)."""
+    nw = (q.bit_length() + 63) // 64
+    return to_ints(uniform_residues(g, q, n, nw))
+
+
 def uniform_scalar(g: np.random.Generator, q: int, limbs: int) -> int:
     return to_ints(uniform_residues(g, q, 1, limbs))[0]
 
@@ -192,6 +199,13 @@ def config_fused(pairs: int = 256, log2n: int = 14, seed_base: int = 4000):
     a = uniform_residues(g, q, pairs * n, 2).reshape(pairs, n, 2)
     b = uniform_residues(g, q, pairs * n, 2).reshape(pairs, n, 2)
     return q, a, b
+
+
+def config_rns(count: int = 8, log2n: int = 16, bits: int = 124, seed_base: int = 7000):
+    """RNS form of polynomials (the FHE shape): `count` NTT-friendly primes of
+    `bits` bits sharing N = 2^log2n.  Returns the list of primes; a polynomial
+    mod Q = prod(q_i) is held as one residue polynomial per prime."""
+    return [find_prime(bits, seed_base + 1 + i) for i in range(count)]
 
 
 def serving_stream(num: int, rate: float = 20000.0, seed: int = 5000,

@@ -216,6 +216,46 @@ def test_largest_length_all_ops(bits):
     batch.destroy()
 
 
+def test_rns_products_recombine_by_crt():
+    """One product of polynomials mod Q = q_1*...*q_4 (two 124-bit and two
+    60-bit primes, N = 2^12) held in RNS form: four product jobs, one per
+    prime, in one batch; the Chinese-remainder recombination of the four
+    results equals the product mod Q (sampled, from the definition)."""
+    require_gpu()
+    import torch
+    widths = [(124, 71), (124, 72), (60, 73), (60, 74)]
+    Q = 1
+    for bits, seed in widths:
+        Q *= prime(bits, seed)
+    log2n, n = 12, 1 << 12
+    g = W.rng(7100)
+    a = W.uniform_ints(g, Q, n)
+    b = W.uniform_ints(g, Q, n)
+    jobs, outs = [], []
+    for bits, seed in widths:
+        q, limbs = prime(bits, seed), W.limbs_for_bits(bits)
+        plan = _plan(log2n, bits, seed)
+        x = dev(W.from_ints([v % q for v in a], limbs))
+        y = dev(W.from_ints([v % q for v in b], limbs))
+        c = torch.empty_like(x)
+        jobs.append((plan, mwntt.NTT_JOB_POLYMUL, x, y, c))
+        outs.append((q, limbs, c))
+    batch = mwntt.NttBatch(jobs)
+    announce("rns product", batch.info())
+    batch.run()
+    batch.check()
+    ks = [0, 1, n // 3, n - 1]
+    res = [0] * len(ks)
+    for q, limbs, c in outs:
+        got = host_ints(c, limbs)
+        m = Q // q
+        coef = m * pow(m, -1, q)
+        for i, k in enumerate(ks):
+            res[i] = (res[i] + got[k] * coef) % Q
+    assert res == oracle.polymul.negacyclic_at(a, b, Q, ks)
+    batch.destroy()
+
+
 def test_batch_argument_errors():
     require_gpu()
     import torch
