@@ -253,6 +253,30 @@ def main():
     # correctness of the timed outputs: the inverse undid the forward
     assert torch.equal(back, poly), "round trip failed"
 
+    # the same step with its 7 launches captured once in a hipGraph and
+    # replayed: one launch per op as above, without the per-call host work
+    gstream = torch.cuda.Stream()
+    gsp = gstream.cuda_stream
+    gops = [lambda: plan.forward(spec, poly, batch=1, stream=gsp),
+            lambda: plan.inverse(back, spec, batch=1, stream=gsp),
+            lambda: mwntt.vec_mulmod(c_mul, xa, xb, q, limbs, stream=gsp),
+            lambda: mwntt.vec_addmod(c_add, xa, xb, q, limbs, stream=gsp),
+            lambda: mwntt.vec_axpymod(y, alpha, xa, q, limbs, stream=gsp)]
+    for f in gops:
+        f()
+    torch.cuda.synchronize()
+    sgraph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(sgraph, stream=gstream):
+        for f in gops:
+            f()
+    torch.cuda.synchronize()
+    graph_us = time_calls(sgraph.replay, torch.cuda.current_stream(), reps=args.steps)
+    back.zero_()
+    sgraph.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(back, poly), "graph-replayed round trip failed"
+    del sgraph
+
     # per-op latency, each op bracketed by events on its stream (paper protocol:
     # mean of the last half of the runs; here also p50 / p99)
     lat = {}
@@ -495,6 +519,8 @@ def main():
         # binding); close to ms_per_step means the plain step is bound by
         # call submission rather than by the GPU
         "host_issue_us_per_step": round(t_enq / args.steps * 1e6, 2),
+        "plain_step_graph": {"us_per_step": round(graph_us, 2), "ntt_s": round(2.0 / (graph_us * 1e-6), 1),
+                             "note": "the same step (7 launches, one per op) captured once in a hipGraph"},
     }
     if args.copy_calibration_mib:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
