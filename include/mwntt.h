@@ -157,10 +157,10 @@ int ntt_forward_pass(ntt_plan_t plan, uint32_t pass, void* d_out, const void* d_
 /* Batched executor: many jobs -- forward or inverse transforms, or fused     */
 /* negacyclic products c = INTT(NTT(a) * NTT(b)) (Background, polynomial     */
 /* multiplication using NTT; the schoolbook product reduced mod X^N + 1) --  */
-/* of any mix of lengths (2^6 .. 2^17) and one- or two-word modulus widths   */
-/* (four-word plans are rejected with MW_EMODULUS), run as one kernel        */
-/* launch per phase (two for transforms, three when a product is present),   */
-/* each launch covering every job.                                           */
+/* of any mix of lengths (2^6 .. 2^17) and modulus widths, run as one       */
+/* kernel launch per phase (two for transforms, three when a product is      */
+/* present), each launch covering every job; four-word jobs' tiles take a   */
+/* second launch in each phase (a kernel of their own).                      */
 /* ------------------------------------------------------------------------ */
 typedef struct ntt_batch_s* ntt_batch_t;
 

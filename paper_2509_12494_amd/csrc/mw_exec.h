@@ -19,12 +19,19 @@ struct PlanView {
   const void* tw_fwd;
   const void* tw_inv;
 };
-bool plan_view(const ntt_plan_s* P, PlanView& v, Modulus<4>& m4, Tw<4>& n4, Tw<4>& l4, Modulus<2>& m2, Tw<2>& n2,
-               Tw<2>& l2);
+template <int W>
+struct ModConst {
+  Modulus<W> M;
+  Tw<W> ninv, last;
+};
+// Per-width constants of a plan: exactly one of c8 / c4 / c2 is filled (by
+// limb count), the others are left as they are.
+bool plan_view(const ntt_plan_s* P, PlanView& v, ModConst<8>& c8, ModConst<4>& c4, ModConst<2>& c2);
 
 enum { JOB_FWD = 0, JOB_INV = 1, JOB_MUL = 2 };
 constexpr int kExecThreads = 256;
-constexpr int kLogP4 = 2;   // points per lane, two-word moduli
+constexpr int kLogP8 = 1;   // points per lane, four-word moduli
+constexpr int kLogP4 = 2;   // two-word moduli
 constexpr int kLogP2 = 3;   // one-word moduli
 
 struct JobDesc {
@@ -37,37 +44,51 @@ struct JobDesc {
   u32 nphases;
 };
 
-template <int W>
-struct ModConst {
-  Modulus<W> M;
-  Tw<W> ninv, last;
-};
-
 // Host-side description of one run: descriptors, tile list per phase, LDS
 // per phase, scratch per job (bytes; JobDesc::scratch is filled in by the
 // owner of the scratch memory).
+// Tiles of four-word jobs go to their own list and kernel (their residues
+// take twice the registers, which would lower the occupancy of every tile if
+// one kernel ran both).
 struct ExecPlan {
   std::vector<JobDesc> jobs;
+  std::vector<ModConst<8>> m8;
   std::vector<ModConst<4>> m4;
   std::vector<ModConst<2>> m2;
-  std::vector<uint2> items;
+  std::vector<uint2> items;        // tiles of one- and two-word jobs
+  std::vector<uint2> items8;       // tiles of four-word jobs
   std::vector<size_t> scratch_bytes;
   u32 phase_begin[4] = {0, 0, 0, 0};
+  u32 phase_begin8[4] = {0, 0, 0, 0};
   u32 nphases = 0;
   size_t phase_lds[3] = {0, 0, 0};
+  size_t phase_lds8[3] = {0, 0, 0};
 };
 
 // Validates the jobs and fills `out` (no device work).  Status as mwntt.h.
 int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out);
-// Raises the kernel's LDS limit when a run needs more than 64 KiB (once).
-hipError_t exec_prepare(size_t max_lds);
-// Launches the phases of a run whose descriptors are already on the device.
-hipError_t exec_launch(const JobDesc* d_jobs, const uint2* d_items, const ModConst<4>* d_m4,
-                       const ModConst<2>* d_m2, const ExecPlan& plan, hipStream_t s);
+// Raises the kernels' LDS limit when a run needs more than 64 KiB (once).
+hipError_t exec_prepare(const ExecPlan& plan);
+
+// Device copies of a run's descriptors (d_items8 / d_m8 may be null when the
+// run has no four-word job).
+struct ExecDevice {
+  const JobDesc* jobs;
+  const uint2* items;
+  const uint2* items8;
+  const ModConst<8>* m8;
+  const ModConst<4>* m4;
+  const ModConst<2>* m2;
+};
+// Launches the phases of a run whose descriptors are already on the device:
+// per phase one launch over the one- and two-word tiles and one over the
+// four-word tiles (each only when the phase has such tiles).
+hipError_t exec_launch(const ExecDevice& d, const ExecPlan& plan, hipStream_t s);
 
 struct ExecParams {
   const JobDesc* jobs;
   const uint2* items;      // this launch's tiles: {job, phase << 16 | tile}
+  const ModConst<8>* mods8;
   const ModConst<4>* mods4;
   const ModConst<2>* mods2;
 };

@@ -8,7 +8,8 @@
 // and b, a fused row phase, the inverse column pass).  Launch k runs every
 // job's phase-k tiles, one workgroup per tile, whatever their length or
 // width; stream order provides the dependencies between phases.  A run is two
-// or three launches with no allocation and no memset, so it can be captured
+// or three launches (twice that when four-word jobs are mixed in: they run in
+// a kernel of their own) with no allocation and no memset, so it can be captured
 // in a hipGraph and replayed.
 //
 // Dependencies are not resolved inside one launch on purpose: the L2 caches of
@@ -17,8 +18,8 @@
 // hand-off, which costs more than the launch it would save.
 //
 // The tiles run the run-time line engine of mw_ntt_rt.h with 4 points per
-// lane for two-word moduli and 8 for one-word moduli (the shapes the
-// autotuner found best for batches), 256 lanes per workgroup.
+// lane for two-word moduli, 8 for one-word and 2 for four-word moduli (the
+// shapes the autotuner found best for batches), 256 lanes per workgroup.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,7 +36,8 @@ template <int W, int LOGP>
 __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J, u32 job, u32 phase, u32 tile,
                                          unsigned char* smem) {
   const ModConst<W>* mc;
-  if constexpr (W == 4) mc = ep.mods4 + job;
+  if constexpr (W == 8) mc = ep.mods8 + job;
+  else if constexpr (W == 4) mc = ep.mods4 + job;
   else mc = ep.mods2 + job;
   NttParams<W> p;
   p.M = mc->M;
@@ -100,6 +102,15 @@ __global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(4)
   else run_item<2, kLogP2>(ep, J, job, phase, tile, mw_exec_smem);
 }
 
+// The tiles of four-word jobs (their own launch: see ExecPlan).
+__global__ __launch_bounds__(kExecThreads) void exec_kernel8(ExecParams ep) {
+  extern __shared__ __align__(16) unsigned char mw_exec_smem[];
+  const uint2 it = ep.items[blockIdx.x];
+  const u32 job = it.x, phase = it.y >> 16, tile = it.y & 0xffffu;
+  const JobDesc J = ep.jobs[job];
+  run_item<8, kLogP8>(ep, J, job, phase, tile, mw_exec_smem);
+}
+
 // host twin of xcd_tile: the tile that position b of a run of n tiles takes
 static u32 xcd_order(u32 b, u32 n) {
   const u32 full = n - n % 8;
@@ -116,6 +127,7 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
   if (!jobs || count == 0 || count > 65535) return MW_EINVAL;
   out = ExecPlan();
   out.jobs.resize(count);
+  out.m8.resize(count);
   out.m4.resize(count);
   out.m2.resize(count);
   out.scratch_bytes.resize(count);
@@ -124,12 +136,13 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
     if (!jb.plan || !jb.in || !jb.out || jb.op > NTT_JOB_POLYMUL) return MW_EINVAL;
     if (jb.op == NTT_JOB_POLYMUL && !jb.in2) return MW_EINVAL;
     PlanView v;
+    ModConst<8>& c8 = out.m8[i];
     ModConst<4>& c4 = out.m4[i];
     ModConst<2>& c2 = out.m2[i];
+    c8 = {};
     c4 = {};
     c2 = {};
-    if (!plan_view(jb.plan, v, c4.M, c4.ninv, c4.last, c2.M, c2.ninv, c2.last)) return MW_EINVAL;
-    if (v.limbs != 1 && v.limbs != 2) return MW_EMODULUS;   // four-word moduli: plain entry points only
+    if (!plan_view(jb.plan, v, c8, c4, c2)) return MW_EINVAL;
     if (v.log2n < 6) return MW_ESIZE;   // two-pass tiles need N1, N2 >= 8
     if (jb.op == NTT_JOB_POLYMUL && check_modulus(v.q, v.limbs, true) != MW_OK) return MW_EMODULUS;
     JobDesc& d = out.jobs[i];
@@ -145,7 +158,7 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
     d.log_n1 = v.log2n / 2;
     d.perm_out = !(v.flags & NTT_BITREV_OUT);
     d.perm_in = !(v.flags & NTT_BITREV_IN);
-    const u32 logp = v.limbs == 2 ? kLogP4 : kLogP2;
+    const u32 logp = v.limbs == 4 ? kLogP8 : (v.limbs == 2 ? kLogP4 : kLogP2);
     const u32 l1 = d.log_n1, l2 = v.log2n - d.log_n1;
     const u32 tpl_c = 1u << (l1 - logp), tpl_r = 1u << (l2 - logp);
     d.lines_col = std::min<u32>(kExecThreads / tpl_c, 1u << l2);
@@ -153,7 +166,7 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
     const u32 ncol = (1u << l2) / d.lines_col, nrow = (1u << l1) / d.lines_row;
     const size_t rsz = 8 * (size_t)v.limbs;
     const size_t lds_c = d.lines_col * npad_of(l1, logp) * rsz, lds_r = d.lines_row * npad_of(l2, logp) * rsz;
-    size_t* pl = out.phase_lds;
+    size_t* pl = v.limbs == 4 ? out.phase_lds8 : out.phase_lds;
     if (d.op == JOB_FWD) {
       d.nphases = 2; d.tiles[0] = ncol; d.tiles[1] = nrow;
       pl[0] = std::max(pl[0], lds_c);
@@ -170,52 +183,73 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
     }
     out.scratch_bytes[i] = (d.op == JOB_MUL ? 2 : 1) * (rsz << v.log2n);
   }
-  for (size_t l : out.phase_lds)
-    if (l > 160 * 1024) return MW_ESIZE;
+  for (int k = 0; k < 3; ++k)
+    if (out.phase_lds[k] > 160 * 1024 || out.phase_lds8[k] > 160 * 1024) return MW_ESIZE;
   // tiles, phase-major: launch k covers [phase_begin[k], phase_begin[k+1]).
   // Workgroup b of a launch runs on XCD b mod 8 and each XCD has its own L2;
   // neighbouring column tiles read parts of the same cache lines, so a job's
   // run of column tiles is laid out such that consecutive tiles share an XCD
   // (the order xcd_tile gives).  Row tiles keep their order: the tiles that
   // write one output line are already a multiple of 8 apart.
+  // Four-word jobs' tiles go to items8 in the same order.
   for (u32 ph = 0; ph < 3; ++ph) {
     out.phase_begin[ph] = (u32)out.items.size();
+    out.phase_begin8[ph] = (u32)out.items8.size();
     for (uint32_t i = 0; i < count; ++i) {
       const JobDesc& d = out.jobs[i];
       if (ph >= d.nphases) continue;
+      std::vector<uint2>& list = d.limbs == 4 ? out.items8 : out.items;
       const bool col = d.op == JOB_FWD ? ph == 0 : (d.op == JOB_INV ? ph == 1 : ph != 1);
       const u32 n = d.tiles[ph];
       for (u32 b = 0; b < n; ++b) {
         const u32 t = col ? xcd_order(b, n) : b;
-        out.items.push_back(make_uint2(i, (ph << 16) | t));
+        list.push_back(make_uint2(i, (ph << 16) | t));
       }
     }
-    if (out.items.size() > out.phase_begin[ph]) out.nphases = ph + 1;
+    if (out.items.size() > out.phase_begin[ph] || out.items8.size() > out.phase_begin8[ph]) out.nphases = ph + 1;
   }
   out.phase_begin[3] = (u32)out.items.size();
+  out.phase_begin8[3] = (u32)out.items8.size();
   return MW_OK;
 }
 
-hipError_t exec_prepare(size_t max_lds) {
-  if (max_lds <= 65536) return hipSuccess;
-  static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(exec_kernel),
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  return e;
+hipError_t exec_prepare(const ExecPlan& plan) {
+  const size_t lds = std::max(plan.phase_lds[0], std::max(plan.phase_lds[1], plan.phase_lds[2]));
+  const size_t lds8 = std::max(plan.phase_lds8[0], std::max(plan.phase_lds8[1], plan.phase_lds8[2]));
+  if (lds > 65536) {
+    static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(exec_kernel),
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  if (lds8 > 65536) {
+    static const hipError_t e8 = hipFuncSetAttribute(reinterpret_cast<const void*>(exec_kernel8),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e8 != hipSuccess) return e8;
+  }
+  return hipSuccess;
 }
 
-hipError_t exec_launch(const JobDesc* d_jobs, const uint2* d_items, const ModConst<4>* d_m4,
-                       const ModConst<2>* d_m2, const ExecPlan& plan, hipStream_t s) {
+hipError_t exec_launch(const ExecDevice& d, const ExecPlan& plan, hipStream_t s) {
   ExecParams ep;
-  ep.jobs = d_jobs;
-  ep.mods4 = d_m4;
-  ep.mods2 = d_m2;
+  ep.jobs = d.jobs;
+  ep.mods8 = d.m8;
+  ep.mods4 = d.m4;
+  ep.mods2 = d.m2;
   for (u32 k = 0; k < plan.nphases; ++k) {
     const u32 n = plan.phase_begin[k + 1] - plan.phase_begin[k];
-    if (n == 0) continue;
-    ep.items = d_items + plan.phase_begin[k];
-    hipLaunchKernelGGL(exec_kernel, dim3(n), dim3(kExecThreads), plan.phase_lds[k], s, ep);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (n) {
+      ep.items = d.items + plan.phase_begin[k];
+      hipLaunchKernelGGL(exec_kernel, dim3(n), dim3(kExecThreads), plan.phase_lds[k], s, ep);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    const u32 n8 = plan.phase_begin8[k + 1] - plan.phase_begin8[k];
+    if (n8) {
+      ep.items = d.items8 + plan.phase_begin8[k];
+      hipLaunchKernelGGL(exec_kernel8, dim3(n8), dim3(kExecThreads), plan.phase_lds8[k], s, ep);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -229,6 +263,8 @@ struct ntt_batch_s {
   ExecPlan plan;
   JobDesc* d_jobs = nullptr;
   uint2* d_items = nullptr;
+  uint2* d_items8 = nullptr;
+  ModConst<8>* d_m8 = nullptr;
   ModConst<4>* d_m4 = nullptr;
   ModConst<2>* d_m2 = nullptr;
   void* d_scratch = nullptr;
@@ -240,6 +276,8 @@ void free_batch(ntt_batch_s* B) {
   if (!B) return;
   if (B->d_jobs) (void)hipFree(B->d_jobs);
   if (B->d_items) (void)hipFree(B->d_items);
+  if (B->d_items8) (void)hipFree(B->d_items8);
+  if (B->d_m8) (void)hipFree(B->d_m8);
   if (B->d_m4) (void)hipFree(B->d_m4);
   if (B->d_m2) (void)hipFree(B->d_m2);
   if (B->d_scratch) (void)hipFree(B->d_scratch);
@@ -282,10 +320,11 @@ extern "C" int ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t 
     for (uint32_t i = 0; i < count; ++i) B->plan.jobs[i].scratch = (u64)((char*)B->d_scratch + off[i]);
   if (st == MW_OK) st = upload(&B->d_jobs, B->plan.jobs);
   if (st == MW_OK) st = upload(&B->d_items, B->plan.items);
+  if (st == MW_OK) st = upload(&B->d_items8, B->plan.items8);
+  if (st == MW_OK) st = upload(&B->d_m8, B->plan.m8);
   if (st == MW_OK) st = upload(&B->d_m4, B->plan.m4);
   if (st == MW_OK) st = upload(&B->d_m2, B->plan.m2);
-  const size_t max_lds = std::max(B->plan.phase_lds[0], std::max(B->plan.phase_lds[1], B->plan.phase_lds[2]));
-  if (st == MW_OK && exec_prepare(max_lds) != hipSuccess) st = MW_EDEVICE;
+  if (st == MW_OK && exec_prepare(B->plan) != hipSuccess) st = MW_EDEVICE;
   if (st != MW_OK) {
     free_batch(B);
     return st;
@@ -296,16 +335,22 @@ extern "C" int ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t 
 
 extern "C" int ntt_batch_run(ntt_batch_t batch, void* stream) {
   if (!batch) return MW_EINVAL;
-  return exec_launch(batch->d_jobs, batch->d_items, batch->d_m4, batch->d_m2, batch->plan,
-                     reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+  const ExecDevice d{batch->d_jobs, batch->d_items, batch->d_items8, batch->d_m8, batch->d_m4, batch->d_m2};
+  return exec_launch(d, batch->plan, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
              ? MW_OK
              : MW_EDEVICE;
 }
 
 extern "C" int ntt_batch_info(ntt_batch_t batch, uint32_t* tiles, uint32_t* launches) {
   if (!batch) return MW_EINVAL;
-  if (tiles) *tiles = (uint32_t)batch->plan.items.size();
-  if (launches) *launches = batch->plan.nphases;
+  if (tiles) *tiles = (uint32_t)(batch->plan.items.size() + batch->plan.items8.size());
+  if (launches) {
+    const ExecPlan& P = batch->plan;
+    uint32_t n = 0;
+    for (u32 k = 0; k < P.nphases; ++k)
+      n += (P.phase_begin[k + 1] > P.phase_begin[k]) + (P.phase_begin8[k + 1] > P.phase_begin8[k]);
+    *launches = n;
+  }
   return MW_OK;
 }
 

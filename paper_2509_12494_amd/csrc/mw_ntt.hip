@@ -14,6 +14,7 @@
 
 #include "mw_arith.h"
 #include "mw_common.h"
+#include "mw_exec.h"
 #include "mw_ntt_tile.h"
 #include "mw_tuned.h"
 
@@ -353,16 +354,9 @@ int ensure_scratch(ntt_plan_s* P) {
 }  // namespace
 
 namespace mw {
-struct PlanView {
-  uint32_t log2n, limbs, flags;
-  const uint64_t* q;
-  const void* tw_fwd;
-  const void* tw_inv;
-};
-
-// Read access to a plan for the batched executor (mw_exec.hip).
-bool plan_view(const ntt_plan_s* P, PlanView& v, Modulus<4>& m4, Tw<4>& n4, Tw<4>& l4, Modulus<2>& m2, Tw<2>& n2,
-               Tw<2>& l2) {
+// Read access to a plan for the batched executor (mw_exec.hip) and the
+// serving runtime: the layout fields and the constants of its width.
+bool plan_view(const ntt_plan_s* P, PlanView& v, ModConst<8>& c8, ModConst<4>& c4, ModConst<2>& c2) {
   if (!P) return false;
   v.log2n = P->log2n;
   v.limbs = P->limbs;
@@ -370,12 +364,19 @@ bool plan_view(const ntt_plan_s* P, PlanView& v, Modulus<4>& m4, Tw<4>& n4, Tw<4
   v.q = P->q;
   v.tw_fwd = P->d_tw_fwd;
   v.tw_inv = P->d_tw_inv;
-  m4 = P->M4;
-  n4 = P->ninv4;
-  l4 = P->last4;
-  m2 = P->M2;
-  n2 = P->ninv2;
-  l2 = P->last2;
+  if (P->limbs == 4) {
+    c8.M = P->M8;
+    c8.ninv = P->ninv8;
+    c8.last = P->last8;
+  } else if (P->limbs == 2) {
+    c4.M = P->M4;
+    c4.ninv = P->ninv4;
+    c4.last = P->last4;
+  } else {
+    c2.M = P->M2;
+    c2.ninv = P->ninv2;
+    c2.last = P->last2;
+  }
   return true;
 }
 }  // namespace mw

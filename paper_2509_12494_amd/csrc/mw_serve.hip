@@ -203,9 +203,11 @@ bool launch_batch(mw_server_s* S, Slot& slot, const std::vector<uint64_t>& batch
         hipMemcpyAsync(slot.d_m4, slot.h_m4, sizeof(ModConst<4>) * nj, hipMemcpyHostToDevice, slot.stream) != hipSuccess ||
         hipMemcpyAsync(slot.d_m2, slot.h_m2, sizeof(ModConst<2>) * nj, hipMemcpyHostToDevice, slot.stream) != hipSuccess)
       return false;
-    const size_t max_lds = std::max(plan.phase_lds[0], std::max(plan.phase_lds[1], plan.phase_lds[2]));
-    if (exec_prepare(max_lds) != hipSuccess) return false;
-    if (exec_launch(slot.d_jobs, slot.d_items, slot.d_m4, slot.d_m2, plan, slot.stream) != hipSuccess) return false;
+    if (exec_prepare(plan) != hipSuccess) return false;
+    // requests carry one- and two-word moduli only (validate), so there are
+    // no four-word tiles
+    const ExecDevice d{slot.d_jobs, slot.d_items, nullptr, nullptr, slot.d_m4, slot.d_m2};
+    if (exec_launch(d, plan, slot.stream) != hipSuccess) return false;
   }
   for (uint64_t t : batch) {
     Req& R = S->reqs[t];
@@ -315,12 +317,11 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
   if (is_ntt(op)) {
     if (!r.plan) return MW_EINVAL;
     PlanView v;
-    Modulus<4> m4;
-    Tw<4> a4, b4;
-    Modulus<2> m2;
-    Tw<2> a2, b2;
-    if (!plan_view(r.plan, v, m4, a4, b4, m2, a2, b2)) return MW_EINVAL;
-    if (v.limbs != 1 && v.limbs != 2) return MW_EMODULUS;   // the executor takes one- and two-word moduli
+    ModConst<8> c8;
+    ModConst<4> c4;
+    ModConst<2> c2;
+    if (!plan_view(r.plan, v, c8, c4, c2)) return MW_EINVAL;
+    if (v.limbs != 1 && v.limbs != 2) return MW_EMODULUS;   // requests: one- and two-word moduli
     if (v.log2n < 6) return MW_ESIZE;
     if (op == MW_REQ_POLYMUL) {
       if (!r.in2) return MW_EINVAL;

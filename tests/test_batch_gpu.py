@@ -216,6 +216,73 @@ def test_largest_length_all_ops(bits):
     batch.destroy()
 
 
+def test_three_widths_in_one_batch():
+    """60-, 124- and 252-bit jobs (forward, inverse, product; N = 2^6..2^10) in
+    one batch: the four-word tiles run in a kernel of their own in each phase;
+    every output against the oracle in full."""
+    require_gpu()
+    import torch
+    specs = [(6, 252), (7, 60), (8, 124), (8, 252), (9, 252), (10, 124), (10, 252), (7, 252), (9, 60)]
+    jobs, checks = [], []
+    for k, (log2n, bits) in enumerate(specs):
+        plan = _plan(log2n, bits, 45 + k % 2)
+        q, limbs, n = plan.q, plan.limbs, plan.n
+        g = W.rng(800 + k)
+        A, B = W.uniform_residues(g, q, n, limbs), W.uniform_residues(g, q, n, limbs)
+        a, b = dev(A), dev(B)
+        out = torch.empty_like(a)
+        a_i, b_i = W.to_ints(A), W.to_ints(B)
+        op = k % 3
+        if op == 0:
+            jobs.append((plan, mwntt.NTT_JOB_FORWARD, a, None, out))
+            checks.append((out, limbs, oracle.ntt.ntt_negacyclic(a_i, q)))
+        elif op == 1:
+            jobs.append((plan, mwntt.NTT_JOB_INVERSE, a, None, out))
+            checks.append((out, limbs, oracle.ntt.intt_negacyclic(a_i, q)))
+        else:
+            jobs.append((plan, mwntt.NTT_JOB_POLYMUL, a, b, out))
+            checks.append((out, limbs, oracle.polymul.negacyclic(a_i, b_i, q)))
+    batch = mwntt.NttBatch(jobs)
+    info = batch.info()
+    announce("batch three widths", info)
+    assert info["launches"] > 3   # phases with four-word tiles take a second launch
+    for rep in range(2):
+        for out, _, _ in checks:
+            out.zero_()
+        batch.run()
+        batch.check()
+        for i, (out, limbs, want) in enumerate(checks):
+            assert host_ints(out, limbs) == want, f"run {rep} job {i}"
+    batch.destroy()
+
+
+def test_252bit_product_2e16_sampled():
+    """A 252-bit negacyclic product at N = 2^16 through the executor, against
+    plain forward / vec_mulmod / inverse and sampled schoolbook outputs."""
+    require_gpu()
+    import torch
+    plan = _plan(16, 252, 47)
+    q, n = plan.q, plan.n
+    g = W.rng(900)
+    A, B = W.uniform_residues(g, q, n, 4), W.uniform_residues(g, q, n, 4)
+    a, b = dev(A), dev(B)
+    c = torch.empty_like(a)
+    batch = mwntt.NttBatch([(plan, mwntt.NTT_JOB_POLYMUL, a, b, c)])
+    batch.run()
+    batch.check()
+    fa, fb = torch.empty_like(a), torch.empty_like(b)
+    plan.forward(fa, a)
+    plan.forward(fb, b)
+    mwntt.vec_mulmod(fa, fa, fb, q, 4)
+    plan.inverse(fb, fa)
+    torch.cuda.synchronize()
+    assert torch.equal(fb, c)
+    ks = [0, 1, n // 2, n - 1]
+    got = host_ints(c, 4)
+    assert [got[k] for k in ks] == oracle.polymul.negacyclic_at(W.to_ints(A), W.to_ints(B), q, ks)
+    batch.destroy()
+
+
 def test_rns_products_recombine_by_crt():
     """One product of polynomials mod Q = q_1*...*q_4 (two 124-bit and two
     60-bit primes, N = 2^12) held in RNS form: four product jobs, one per
@@ -268,9 +335,10 @@ def test_batch_argument_errors():
     y = torch.zeros(256, 1, dtype=torch.int64, device="cuda")
     with pytest.raises(mwntt.MwError):
         mwntt.NttBatch([(p60, mwntt.NTT_JOB_POLYMUL, y, None, y)])   # product without b
-    p252 = mwntt.ntt_plan(8, prime(252, 41), 4)   # four-word moduli: plain entry points only
+    p200 = mwntt.ntt_plan(8, prime(200, 41), 4)   # four-word product below Barrett's 225 bits
     z = torch.zeros(256, 4, dtype=torch.int64, device="cuda")
     with pytest.raises(mwntt.MwError) as e:
-        mwntt.NttBatch([(p252, mwntt.NTT_JOB_FORWARD, z, None, z)])
+        mwntt.NttBatch([(p200, mwntt.NTT_JOB_POLYMUL, z, z, z)])
     assert e.value.status == -2
-    p252.destroy()
+    mwntt.NttBatch([(p200, mwntt.NTT_JOB_FORWARD, z, None, z)]).destroy()   # transforms are fine
+    p200.destroy()
