@@ -45,10 +45,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(pass_):
-    """HBM bytes per launch of the pass from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy of known size), or None
-    when the summary is missing or the kernel sources changed since."""
+def _profile_value(key):
+    """A `- key: value` line of the committed rocprofv3 summary, or None when
+    the summary is missing or the kernel sources changed since it was taken."""
     try:
         lines = open(PROFILE).read().splitlines()
     except OSError:
@@ -57,8 +56,19 @@ def measured_traffic(pass_):
     kv = {k[2:].strip(): v.strip() for k, v in kv.items()}
     if kv.get("source_hash") != kernel_source_hash():
         return None
-    v = kv.get(f"traffic_bytes_pass{pass_}")
+    v = kv.get(key)
     return int(v) if v else None
+
+
+def measured_traffic(pass_):
+    """HBM bytes per launch of the pass (FETCH_SIZE + WRITE_SIZE scaled by a
+    copy of known size)."""
+    return _profile_value(f"traffic_bytes_pass{pass_}")
+
+
+def measured_valu(pass_):
+    """VALU wave-instructions per launch of the pass (SQ_INSTS_VALU)."""
+    return _profile_value(f"valu_insts_pass{pass_}")
 
 
 def butterfly_word_ops(W):
@@ -481,6 +491,14 @@ def main():
     d = passes[dom]
     achieved_tops = d["ops"] / (d["us"] * 1e-6) / 1e12
     traffic = measured_traffic(dom)
+    valu_insts = measured_valu(dom)
+    valu_issue = None
+    if valu_insts:
+        # what the kernel issues, beside the algorithmic count: VALU
+        # wave-instructions x 64 lanes per launch, over the same launch time
+        issued = valu_insts * 64 / (d["us"] * 1e-6) / 1e12
+        valu_issue = {"valu_insts": valu_insts, "lane_ops_per_butterfly": round(valu_insts * 64 / (d["ops"] / butterfly_word_ops(W_words)), 1),
+                      "achieved": round(issued, 3), "frac": round(issued / INT32_PEAK_TOPS, 4)}
 
     mulmods_step = 2 * bfly + 2 * n        # two transforms + vec_mulmod + vec_axpymod
     res = {
@@ -511,6 +529,7 @@ def main():
                      "achieved": round(achieved_tops, 3), "peak": round(INT32_PEAK_TOPS, 2),
                      "unit": "Tint32op/s", "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": traffic,
                      "launch_us": round(d["us"], 3), "ops_per_butterfly": butterfly_word_ops(W_words),
+                     "valu_issue": valu_issue,
                      "algorithmic_bytes": d["bytes"],
                      "hbm_gbs_algorithmic": round(d["bytes"] / (d["us"] * 1e-6) / 1e9, 1),
                      "passes_us": {str(k): round(v["us"], 3) for k, v in passes.items()}},

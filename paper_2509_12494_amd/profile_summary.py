@@ -3,6 +3,7 @@
 
     python -m paper_2509_12494_amd.profile_summary kernels RESULTS.db [--match mw::] [--top N]
     python -m paper_2509_12494_amd.profile_summary counters FETCH.db WRITE.db --copy-bytes BYTES [--match mw::] [--top N]
+    python -m paper_2509_12494_amd.profile_summary valu VALU.db [--match mw::] [--top N]
 
 `kernels` lists every kernel (grouped by name and grid size) with its launch
 count and average / min / max duration.  `counters` reads FETCH_SIZE and
@@ -67,6 +68,29 @@ def counters(fetch_db, write_db, copy_bytes, match=None):
     return {"fetch_factor": fs, "write_factor": ws, "copy_fetch_raw": fraw, "copy_write_raw": wraw, "rows": out}
 
 
+def valu(db, match=None):
+    """Per kernel (name, grid): VALU wave-instructions, waves and the share
+    of cycles the SQ had work (SQ_BUSY_CYCLES / SQ_CYCLES), averaged over
+    dispatches."""
+    con = sqlite3.connect(db)
+    q = ("select kernel_name, grid_size, workgroup_size, counter_name, avg(value), count(*) "
+         "from counters_collection group by kernel_name, grid_size, counter_name")
+    rows = {}
+    for k, g, w, c, v, n in con.execute(q):
+        if match and match not in k:
+            continue
+        rows.setdefault((_short(k), g // max(w, 1)), {})[c] = (v, n)
+    out = []
+    for (k, g), d in rows.items():
+        insts, n = d.get("SQ_INSTS_VALU", (0, 0))
+        waves = d.get("SQ_WAVES", (0, 0))[0]
+        busy = d.get("SQ_BUSY_CYCLES", (0, 0))[0]
+        cyc = d.get("SQ_CYCLES", (1, 0))[0] or 1
+        out.append((k, g, n, insts, waves, busy / cyc))
+    out.sort(key=lambda r: -r[3] * r[2])
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -80,12 +104,21 @@ def main(argv=None):
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--match", default=None)
     b.add_argument("--top", type=int, default=None)
+    c = sub.add_parser("valu")
+    c.add_argument("db")
+    c.add_argument("--match", default=None)
+    c.add_argument("--top", type=int, default=None)
     args = ap.parse_args(argv)
     if args.cmd == "kernels":
         print("| kernel | workgroups | threads | launches | avg us | min us | max us |")
         print("|---|---|---|---|---|---|---|")
         for r in kernels(args.db, args.match)[:args.top]:
             print(f"| `{r[0]}` | {r[1]} | {r[2]} | {r[3]} | {r[4]:.3f} | {r[5]:.3f} | {r[6]:.3f} |")
+    elif args.cmd == "valu":
+        print("| kernel | workgroups | dispatches | VALU wave-instructions | waves | SQ busy share |")
+        print("|---|---|---|---|---|---|")
+        for k, g, n, i, w, b in valu(args.db, args.match)[:args.top]:
+            print(f"| `{k}` | {g} | {n} | {i:.0f} | {w:.0f} | {b:.3f} |")
     else:
         c = counters(args.fetch_db, args.write_db, args.copy_bytes, args.match)
         print(f"calibration copy of {args.copy_bytes} B: FETCH_SIZE read {c['copy_fetch_raw']:.0f} B "
