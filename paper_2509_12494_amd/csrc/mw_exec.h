@@ -87,7 +87,7 @@ hipError_t exec_launch(const ExecDevice& d, const ExecPlan& plan, hipStream_t s)
 
 struct ExecParams {
   const JobDesc* jobs;
-  const uint2* items;      // this launch's tiles: {job, phase << 16 | tile}
+  const uint2* items;      // this launch's tiles: {job | limbs << 16, phase << 16 | tile}
   const ModConst<8>* mods8;
   const ModConst<4>* mods4;
   const ModConst<2>* mods2;

@@ -95,10 +95,13 @@ __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J,
 
 __global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(4))) void exec_kernel(ExecParams ep) {
   extern __shared__ __align__(16) unsigned char mw_exec_smem[];
+  // item: {job | limbs << 16, phase << 16 | tile}.  The width comes with the
+  // item, so the job descriptor and the modulus constants (both indexed by
+  // the job) load in parallel instead of one after the other.
   const uint2 it = ep.items[blockIdx.x];
-  const u32 job = it.x, phase = it.y >> 16, tile = it.y & 0xffffu;
+  const u32 job = it.x & 0xffffu, limbs = it.x >> 16, phase = it.y >> 16, tile = it.y & 0xffffu;
   const JobDesc J = ep.jobs[job];
-  if (J.limbs == 2) run_item<4, kLogP4>(ep, J, job, phase, tile, mw_exec_smem);
+  if (limbs == 2) run_item<4, kLogP4>(ep, J, job, phase, tile, mw_exec_smem);
   else run_item<2, kLogP2>(ep, J, job, phase, tile, mw_exec_smem);
 }
 
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(4)
 __global__ __launch_bounds__(kExecThreads) void exec_kernel8(ExecParams ep) {
   extern __shared__ __align__(16) unsigned char mw_exec_smem[];
   const uint2 it = ep.items[blockIdx.x];
-  const u32 job = it.x, phase = it.y >> 16, tile = it.y & 0xffffu;
+  const u32 job = it.x & 0xffffu, phase = it.y >> 16, tile = it.y & 0xffffu;
   const JobDesc J = ep.jobs[job];
   run_item<8, kLogP8>(ep, J, job, phase, tile, mw_exec_smem);
 }
@@ -203,7 +206,7 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
       const u32 n = d.tiles[ph];
       for (u32 b = 0; b < n; ++b) {
         const u32 t = col ? xcd_order(b, n) : b;
-        list.push_back(make_uint2(i, (ph << 16) | t));
+        list.push_back(make_uint2(i | (d.limbs << 16), (ph << 16) | t));
       }
     }
     if (out.items.size() > out.phase_begin[ph] || out.items8.size() > out.phase_begin8[ph]) out.nphases = ph + 1;

@@ -13,7 +13,7 @@ import oracle
 from paper_2509_12494_amd import mwntt
 from paper_2509_12494_amd import workloads as W
 
-from .gpu_util import announce, dev, host_ints, prime, require_gpu
+from .gpu_util import announce, bitrev, dev, host_ints, prime, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -281,6 +281,74 @@ def test_252bit_product_2e16_sampled():
     got = host_ints(c, 4)
     assert [got[k] for k in ks] == oracle.polymul.negacyclic_at(W.to_ints(A), W.to_ints(B), q, ks)
     batch.destroy()
+
+
+def _plain(plan, op, a, b):
+    """The job through the plain entry points."""
+    import torch
+    out = torch.empty_like(a)
+    if op == mwntt.NTT_JOB_FORWARD:
+        plan.forward(out, a)
+    elif op == mwntt.NTT_JOB_INVERSE:
+        plan.inverse(out, a)
+    else:
+        fa, fb = torch.empty_like(a), torch.empty_like(b)
+        plan.forward(fa, a)
+        plan.forward(fb, b)
+        mwntt.vec_mulmod(fa, fa, fb, plan.q, plan.limbs)
+        plan.inverse(out, fa)
+    return out
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_mixes_match_plain(seed):
+    """Seeded random batches: 40 jobs, each of random width (60 / 124 / 252
+    bits), N = 2^6..2^14, op and order flags; every output equal to the same
+    job through the plain entry points, and sampled outputs to the oracle."""
+    require_gpu()
+    import torch
+    g = W.rng(9100 + seed)
+    jobs, refs = [], []
+    for k in range(40):
+        bits = int(g.choice([60, 124, 252]))
+        log2n = int(g.integers(6, 15))
+        op = int(g.integers(0, 3))
+        flags = int(g.integers(0, 4)) if op != mwntt.NTT_JOB_POLYMUL else 0
+        q = prime(bits, 50 + k % 3)
+        limbs = W.limbs_for_bits(bits)
+        plan = mwntt.ntt_plan(log2n, q, limbs, flags=flags)
+        n = plan.n
+        A, B = W.uniform_residues(g, q, n, limbs), W.uniform_residues(g, q, n, limbs)
+        a, b = dev(A), dev(B)
+        out = torch.empty_like(a)
+        jobs.append((plan, op, a, b if op == mwntt.NTT_JOB_POLYMUL else None, out))
+        refs.append((plan, op, a, b, out, A, B, flags))
+    batch = mwntt.NttBatch(jobs)
+    announce("random mix", seed, batch.info())
+    batch.run()
+    batch.check()
+    for i, (plan, op, a, b, out, A, B, flags) in enumerate(refs):
+        want = _plain(plan, op, a, b)
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), f"job {i}: op {op}, N {plan.n}, {plan.limbs} limbs, flags {flags}"
+        if i % 8 == 0:
+            n, q = plan.n, plan.q
+            ks = [0, n - 1, (i * 131) % n]
+            got = host_ints(out, plan.limbs)
+            a_i, b_i = W.to_ints(A), W.to_ints(B)
+            if op == mwntt.NTT_JOB_POLYMUL:
+                assert [got[k] for k in ks] == oracle.polymul.negacyclic_at(a_i, b_i, q, ks)
+            elif op == mwntt.NTT_JOB_FORWARD:
+                pos = [bitrev(k, plan.log2n) if flags & mwntt.NTT_BITREV_OUT else k for k in ks]
+                assert [got[p_] for p_ in pos] == oracle.ntt.forward_at(a_i, q, ks)
+            else:
+                src = a_i
+                if flags & mwntt.NTT_BITREV_IN:     # input is a spectrum in bit-reversed order
+                    src = [a_i[bitrev(k, plan.log2n)] for k in range(n)]
+                assert [got[k] for k in ks] == oracle.ntt.inverse_at(src, q, ks)
+    batch.destroy()
+    for plan, *_ in refs:
+        plan.destroy()
 
 
 def test_rns_products_recombine_by_crt():
