@@ -227,17 +227,17 @@ enum mw_request_op {
 };
 
 /* One request.  Transform and product requests take q, N and the width from
- * `plan` (N >= 2^6; one- or two-word moduli, else MW_EMODULUS); BLAS requests
- * take q, limbs (1 or 2, else MW_EINVAL), n (and alpha for axpy:
+ * `plan` (N >= 2^6); BLAS requests take q, limbs (1, 2 or 4; the first
+ * `limbs` words of q and alpha are used), n (and alpha for axpy:
  * out = alpha*in + in2).  `in` / `in2` are device buffers owned by the
  * caller that must stay valid until the request completes; in2 is b for
  * products and BLAS, NULL otherwise. */
 typedef struct {
   uint32_t op;
   ntt_plan_t plan;
-  uint64_t q[2];
+  uint64_t q[4];
   uint32_t limbs;
-  uint64_t alpha[2];
+  uint64_t alpha[4];
   uint64_t n;
   const void* in;
   const void* in2;

@@ -124,10 +124,14 @@ struct Slot {
   hipEvent_t done = nullptr;
   JobDesc* d_jobs = nullptr;
   uint2* d_items = nullptr;
+  uint2* d_items8 = nullptr;
+  ModConst<8>* d_m8 = nullptr;
   ModConst<4>* d_m4 = nullptr;
   ModConst<2>* d_m2 = nullptr;
   JobDesc* h_jobs = nullptr;     // pinned staging
   uint2* h_items = nullptr;
+  uint2* h_items8 = nullptr;
+  ModConst<8>* h_m8 = nullptr;
   ModConst<4>* h_m4 = nullptr;
   ModConst<2>* h_m2 = nullptr;
   bool busy = false;
@@ -191,22 +195,27 @@ bool launch_batch(mw_server_s* S, Slot& slot, const std::vector<uint64_t>& batch
   if (!jobs.empty()) {
     ExecPlan plan;
     if (exec_build(jobs.data(), (uint32_t)jobs.size(), plan) != MW_OK) return false;
-    if (plan.items.size() > (size_t)S->cfg.max_batch * kMaxTilesPerJob) return false;
+    if (plan.items.size() > (size_t)S->cfg.max_batch * kMaxTilesPerJob ||
+        plan.items8.size() > (size_t)S->cfg.max_batch * kMaxTilesPerJob)
+      return false;
     for (size_t i = 0; i < jobs.size(); ++i) plan.jobs[i].scratch = (u64)pool_ptr(S, S->reqs[job_tickets[i]].scratch_off);
-    const size_t nj = plan.jobs.size(), ni = plan.items.size();
+    const size_t nj = plan.jobs.size(), ni = plan.items.size(), ni8 = plan.items8.size();
     std::memcpy(slot.h_jobs, plan.jobs.data(), sizeof(JobDesc) * nj);
     std::memcpy(slot.h_items, plan.items.data(), sizeof(uint2) * ni);
+    std::memcpy(slot.h_items8, plan.items8.data(), sizeof(uint2) * ni8);
+    std::memcpy(slot.h_m8, plan.m8.data(), sizeof(ModConst<8>) * nj);
     std::memcpy(slot.h_m4, plan.m4.data(), sizeof(ModConst<4>) * nj);
     std::memcpy(slot.h_m2, plan.m2.data(), sizeof(ModConst<2>) * nj);
-    if (hipMemcpyAsync(slot.d_jobs, slot.h_jobs, sizeof(JobDesc) * nj, hipMemcpyHostToDevice, slot.stream) != hipSuccess ||
-        hipMemcpyAsync(slot.d_items, slot.h_items, sizeof(uint2) * ni, hipMemcpyHostToDevice, slot.stream) != hipSuccess ||
-        hipMemcpyAsync(slot.d_m4, slot.h_m4, sizeof(ModConst<4>) * nj, hipMemcpyHostToDevice, slot.stream) != hipSuccess ||
-        hipMemcpyAsync(slot.d_m2, slot.h_m2, sizeof(ModConst<2>) * nj, hipMemcpyHostToDevice, slot.stream) != hipSuccess)
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    if (hipMemcpyAsync(slot.d_jobs, slot.h_jobs, sizeof(JobDesc) * nj, h2d, slot.stream) != hipSuccess ||
+        (ni && hipMemcpyAsync(slot.d_items, slot.h_items, sizeof(uint2) * ni, h2d, slot.stream) != hipSuccess) ||
+        (ni8 && hipMemcpyAsync(slot.d_items8, slot.h_items8, sizeof(uint2) * ni8, h2d, slot.stream) != hipSuccess) ||
+        hipMemcpyAsync(slot.d_m8, slot.h_m8, sizeof(ModConst<8>) * nj, h2d, slot.stream) != hipSuccess ||
+        hipMemcpyAsync(slot.d_m4, slot.h_m4, sizeof(ModConst<4>) * nj, h2d, slot.stream) != hipSuccess ||
+        hipMemcpyAsync(slot.d_m2, slot.h_m2, sizeof(ModConst<2>) * nj, h2d, slot.stream) != hipSuccess)
       return false;
     if (exec_prepare(plan) != hipSuccess) return false;
-    // requests carry one- and two-word moduli only (validate), so there are
-    // no four-word tiles
-    const ExecDevice d{slot.d_jobs, slot.d_items, nullptr, nullptr, slot.d_m4, slot.d_m2};
+    const ExecDevice d{slot.d_jobs, slot.d_items, slot.d_items8, slot.d_m8, slot.d_m4, slot.d_m2};
     if (exec_launch(d, plan, slot.stream) != hipSuccess) return false;
   }
   for (uint64_t t : batch) {
@@ -321,7 +330,6 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
     ModConst<4> c4;
     ModConst<2> c2;
     if (!plan_view(r.plan, v, c8, c4, c2)) return MW_EINVAL;
-    if (v.limbs != 1 && v.limbs != 2) return MW_EMODULUS;   // requests: one- and two-word moduli
     if (v.log2n < 6) return MW_ESIZE;
     if (op == MW_REQ_POLYMUL) {
       if (!r.in2) return MW_EINVAL;
@@ -333,12 +341,11 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
     R.cost_us = 1.0 + (double)bytes * v.log2n / 8.0e4;
   } else {
     if (!r.in2 || r.n == 0) return MW_EINVAL;
-    if (r.limbs != 1 && r.limbs != 2) return MW_EINVAL;     // mw_request holds two words of q
     int st = check_modulus(r.q, r.limbs, op == MW_REQ_VEC_MULMOD);
     if (st != MW_OK) return st;
     if (op == MW_REQ_VEC_AXPYMOD) {
-      mwhost::u128 Q = mwhost::from_words(r.q, r.limbs), A = mwhost::from_words(r.alpha, r.limbs);
-      if (A >= Q) return MW_EINVAL;
+      const mwhost::U256 Q = mwhost::u256_from_words(r.q, r.limbs), A = mwhost::u256_from_words(r.alpha, r.limbs);
+      if (!(A < Q)) return MW_EINVAL;
     }
     R.out_bytes = round_up((size_t)8 * r.limbs * r.n);
     R.scratch_bytes = 0;
@@ -354,10 +361,14 @@ void free_server(mw_server_s* S) {
     if (s.done) (void)hipEventDestroy(s.done);
     if (s.d_jobs) (void)hipFree(s.d_jobs);
     if (s.d_items) (void)hipFree(s.d_items);
+    if (s.d_items8) (void)hipFree(s.d_items8);
+    if (s.d_m8) (void)hipFree(s.d_m8);
     if (s.d_m4) (void)hipFree(s.d_m4);
     if (s.d_m2) (void)hipFree(s.d_m2);
     if (s.h_jobs) (void)hipHostFree(s.h_jobs);
     if (s.h_items) (void)hipHostFree(s.h_items);
+    if (s.h_items8) (void)hipHostFree(s.h_items8);
+    if (s.h_m8) (void)hipHostFree(s.h_m8);
     if (s.h_m4) (void)hipHostFree(s.h_m4);
     if (s.h_m2) (void)hipHostFree(s.h_m2);
   }
@@ -392,10 +403,14 @@ extern "C" int mw_server_create(mw_server_t* out, const mw_server_config* cfg) {
       }
       if (hipMalloc(&s.d_jobs, sizeof(JobDesc) * nj) != hipSuccess ||
           hipMalloc(&s.d_items, sizeof(uint2) * ni) != hipSuccess ||
+          hipMalloc(&s.d_items8, sizeof(uint2) * ni) != hipSuccess ||
+          hipMalloc(&s.d_m8, sizeof(ModConst<8>) * nj) != hipSuccess ||
           hipMalloc(&s.d_m4, sizeof(ModConst<4>) * nj) != hipSuccess ||
           hipMalloc(&s.d_m2, sizeof(ModConst<2>) * nj) != hipSuccess ||
           hipHostMalloc(&s.h_jobs, sizeof(JobDesc) * nj) != hipSuccess ||
           hipHostMalloc(&s.h_items, sizeof(uint2) * ni) != hipSuccess ||
+          hipHostMalloc(&s.h_items8, sizeof(uint2) * ni) != hipSuccess ||
+          hipHostMalloc(&s.h_m8, sizeof(ModConst<8>) * nj) != hipSuccess ||
           hipHostMalloc(&s.h_m4, sizeof(ModConst<4>) * nj) != hipSuccess ||
           hipHostMalloc(&s.h_m2, sizeof(ModConst<2>) * nj) != hipSuccess)
         st = MW_ENOMEM;

@@ -41,8 +41,8 @@ MW_EBUSY = -7
 
 
 class MwRequest(ctypes.Structure):
-    _fields_ = [("op", ctypes.c_uint32), ("plan", ctypes.c_void_p), ("q", ctypes.c_uint64 * 2),
-                ("limbs", ctypes.c_uint32), ("alpha", ctypes.c_uint64 * 2), ("n", ctypes.c_uint64),
+    _fields_ = [("op", ctypes.c_uint32), ("plan", ctypes.c_void_p), ("q", ctypes.c_uint64 * 4),
+                ("limbs", ctypes.c_uint32), ("alpha", ctypes.c_uint64 * 4), ("n", ctypes.c_uint64),
                 ("in_", ctypes.c_void_p), ("in2", ctypes.c_void_p)]
 
 
@@ -340,8 +340,8 @@ def make_request(op: int, inp, inp2=None, plan: Optional[NttPlan] = None, q: int
     r.op = op
     r.plan = plan._h.value if plan is not None else None
     if plan is None:
-        r.q = _words(q, limbs, 2)           # requests carry one- or two-word moduli
-        r.alpha = _words(alpha, limbs, 2)
+        r.q = _words(q, limbs)
+        r.alpha = _words(alpha, limbs)
         r.limbs = limbs
         r.n = n
     r.in_ = _ptr(inp)

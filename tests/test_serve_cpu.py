@@ -75,13 +75,18 @@ def test_reject_too_large_and_invalid():
     with pytest.raises(mwntt.MwError) as e:
         srv.submit(mwntt.make_request(mwntt.MW_REQ_NTT_FORWARD, DUMMY))   # no plan
     assert e.value.status == -1
-    with pytest.raises(ValueError):                     # requests hold two words of q
-        mwntt.make_request(mwntt.MW_REQ_VEC_ADDMOD, DUMMY, DUMMY, q=(1 << 251) + 1, limbs=4, n=8)
     r = mwntt.make_request(mwntt.MW_REQ_VEC_ADDMOD, DUMMY, DUMMY, q=Q60, limbs=1, n=8)
-    r.limbs = 4                                         # the C side refuses it too
+    r.limbs = 3                                         # limb counts are 1, 2 or 4
     with pytest.raises(mwntt.MwError) as e:
         srv.submit(r)
     assert e.value.status == -1
+    q252 = W.find_prime(252, 6001)
+    with pytest.raises(mwntt.MwError) as e:             # four-word alpha not reduced
+        srv.submit(mwntt.make_request(mwntt.MW_REQ_VEC_AXPYMOD, DUMMY, DUMMY, q=q252, limbs=4, n=8, alpha=q252))
+    assert e.value.status == -1
+    t4 = srv.submit(mwntt.make_request(mwntt.MW_REQ_VEC_MULMOD, DUMMY, DUMMY, q=q252, limbs=4, n=8))
+    srv.result(t4, wait=True)
+    srv.release(t4)
     t = srv.submit(_req(100))
     assert srv.result(t, wait=True)[0] is None          # dry run: no output buffer
     with pytest.raises(mwntt.MwError):

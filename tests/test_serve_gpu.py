@@ -1,7 +1,8 @@
 """Serving runtime on the GPU: every result in a mixed, batched, overlapping
 stream is bit-identical to the same operation run alone through the plain
 entry points (and to the oracle on sampled outputs), also when a small HBM
-budget forces queueing; an open-loop Poisson replay completes every request."""
+budget forces queueing and when 60-, 124- and 252-bit requests are mixed; an
+open-loop Poisson replay completes every request."""
 import pytest
 
 import oracle
@@ -16,14 +17,14 @@ OPS = [mwntt.MW_REQ_NTT_FORWARD, mwntt.MW_REQ_NTT_INVERSE, mwntt.MW_REQ_POLYMUL,
        mwntt.MW_REQ_VEC_MULMOD, mwntt.MW_REQ_VEC_AXPYMOD, mwntt.MW_REQ_VEC_ADDMOD, mwntt.MW_REQ_VEC_SUBMOD]
 
 
-def _workload(count, seed, log2_range=(10, 13)):
+def _workload(count, seed, log2_range=(10, 13), wide=False):
     import torch
     g = W.rng(seed)
     plans = {}
     items = []
     for i in range(count):
         op = OPS[i % len(OPS)]
-        bits = 60 if g.random() < 0.5 else 124
+        bits = [60, 124, 252][int(g.integers(0, 3))] if wide else (60 if g.random() < 0.5 else 124)
         q = prime(bits, 61 + (i % 2))
         limbs = W.limbs_for_bits(bits)
         if op <= mwntt.MW_REQ_POLYMUL:
@@ -97,11 +98,13 @@ def _oracle_sample(it, ks):
     return [(it["alpha"] * a[k] + b[k]) % q for k in ks]
 
 
-@pytest.mark.parametrize("budget,inflight,batch", [(1 << 30, 1, 32), (1 << 30, 4, 32), (3 << 20, 2, 4)])
-def test_mixed_stream_matches_alone(budget, inflight, batch):
+@pytest.mark.parametrize("budget,inflight,batch,wide", [(1 << 30, 1, 32, False), (1 << 30, 4, 32, False),
+                                                        (3 << 20, 2, 4, False), (1 << 30, 3, 16, True)])
+def test_mixed_stream_matches_alone(budget, inflight, batch, wide):
+    """wide: 60-, 124- and 252-bit requests in one stream."""
     require_gpu()
     import torch
-    items, plans = _workload(56, seed=budget % 1000 + inflight)
+    items, plans = _workload(56, seed=budget % 1000 + inflight, wide=wide)
     srv = mwntt.MwServer(budget, max_inflight=inflight, max_batch=batch)
     announce("serve mixed", budget, inflight, batch)
     tickets = [srv.submit(_request(it)) for it in items]    # a burst: requests queue and batch
