@@ -67,7 +67,8 @@ const char* mw_status_str(int status);
 
 /* ------------------------------------------------------------------------ */
 /* Element-wise modular BLAS (Background, polynomial operations as BLAS).    */
-/* c[i] = (a[i] + b[i]) mod q, etc., for 0 <= i < n.  n == 0 is a no-op.     */
+/* c[i] = (a[i] + b[i]) mod q, etc., for 0 <= i < n.  n == 0 is a no-op;   */
+/* n > 2^40 is MW_EINVAL.                                                    */
 /* Outputs may alias inputs exactly (c == a or c == b); partial overlap is   */
 /* undefined.                                                                */
 /* ------------------------------------------------------------------------ */

@@ -341,6 +341,7 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
     R.cost_us = 1.0 + (double)bytes * v.log2n / 8.0e4;
   } else {
     if (!r.in2 || r.n == 0) return MW_EINVAL;
+    if (r.n > (uint64_t(1) << 40)) return MW_EINVAL;   // the BLAS length limit; keeps 8*limbs*n exact
     int st = check_modulus(r.q, r.limbs, op == MW_REQ_VEC_MULMOD);
     if (st != MW_OK) return st;
     if (op == MW_REQ_VEC_AXPYMOD) {

@@ -75,6 +75,9 @@ def test_reject_too_large_and_invalid():
     with pytest.raises(mwntt.MwError) as e:
         srv.submit(mwntt.make_request(mwntt.MW_REQ_NTT_FORWARD, DUMMY))   # no plan
     assert e.value.status == -1
+    with pytest.raises(mwntt.MwError) as e:             # n beyond the BLAS length limit
+        srv.submit(mwntt.make_request(mwntt.MW_REQ_VEC_ADDMOD, DUMMY, DUMMY, q=Q60, limbs=1, n=1 << 62))
+    assert e.value.status == -1
     r = mwntt.make_request(mwntt.MW_REQ_VEC_ADDMOD, DUMMY, DUMMY, q=Q60, limbs=1, n=8)
     r.limbs = 3                                         # limb counts are 1, 2 or 4
     with pytest.raises(mwntt.MwError) as e:
