@@ -272,3 +272,45 @@ def test_forward_passes_equal_forward(log2n, batch, bits, seed):
     torch.cuda.synchronize()
     assert torch.equal(ref, out)
     plan.destroy()
+
+
+@pytest.mark.parametrize("q,log2n", [(17, 3), (97, 4), (193, 5), (7681, 8), (12289, 10)])
+def test_tiny_primes(q, log2n):
+    """Degenerate small moduli in one word (far below the 60-bit width the lazy
+    ranges are sized for): whole forward and inverse outputs against the oracle,
+    also through the two-pass path where the size allows it."""
+    require_gpu()
+    import torch
+    n = 1 << log2n
+    A = W.uniform_residues(W.rng(q), q, 2 * n, 1)
+    a_i = W.to_ints(A)
+    want = [oracle.ntt.ntt_negacyclic(a_i[i * n:(i + 1) * n], q) for i in range(2)]
+    splits = [0] + ([3] if log2n >= 6 else [])
+    for split in splits:
+        plan = mwntt.ntt_plan(log2n, q, 1)
+        if split:
+            plan.split = split
+        announce("tiny prime", q, log2n, split)
+        y = _run(plan, A, "fwd", batch=2)
+        got = host_ints(y, 1)
+        assert [got[i * n:(i + 1) * n] for i in range(2)] == want, split
+        z = torch.empty_like(y)
+        plan.inverse(z, y, batch=2)
+        torch.cuda.synchronize()
+        assert host_ints(z, 1) == a_i, split
+        plan.destroy()
+
+
+def test_empty_batch_is_a_no_op():
+    require_gpu()
+    import torch
+    q = prime(124, 22)
+    plan = mwntt.ntt_plan(10, q, 2)
+    x = torch.full((1024, 2), 7, dtype=torch.int64, device="cuda")
+    y = x.clone()
+    plan.forward(y, x, batch=0)
+    plan.inverse(y, x, batch=0)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    plan.destroy()
+
