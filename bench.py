@@ -9,10 +9,15 @@ vec_axpymod on length-2^16 vectors, one library call per operation.  Inputs are
 seeded synthetic data already resident in device memory.
 
 Prints one JSON line.  ``value`` is 124-bit NTTs per second of the whole step
-(2 transforms per step).  Extra fields: per-op latency p50/p99 (HIP events on
-the op's stream), algorithmic Gmulmod/s, the batched (many transforms per
-call) rate, the roofline of the dominant kernel call and the CPU oracle's
-rate on a bounded sample.
+(2 transforms per step).  Extra fields: the host issue time per step and the
+same step replayed from a hipGraph; per-op latency p50/p99 (HIP events on the
+op's stream); algorithmic Gmulmod/s; the batched (96 transforms per call)
+rate; ``legs``: the executor on the same batch, a batch sweep, a
+host-inclusive (pinned copies in and out) figure, the mixed 96-polynomial
+batch and its inverse, 256 fused products at 2^14, RNS products over eight
+primes, the 252-bit transform and BLAS, and the serving replay; the roofline
+of the dominant kernel (with HBM traffic and VALU instructions from the
+committed rocprofv3 summary); and the CPU oracle's rate on a bounded sample.
 """
 import argparse
 import json

@@ -18,7 +18,8 @@ Prime recipe: q = c * 2^m + 1 with c drawn uniformly from
 BPSW test).  That gives bitlen(q) = b and q = 1 (mod 2^m); m = 18 makes every
 N <= 2^17 NTT-friendly (q = 1 mod 2N).  b = 124 is the largest width Barrett
 reduction allows for 128-bit arithmetic (Background, modular arithmetic); b = 60
-is the same rule applied to one 64-bit word.
+is the same rule applied to one 64-bit word and b = 252 to four words (the
+larger widths the paper names as a next step, Discussion).
 """
 from __future__ import annotations
 
@@ -30,9 +31,9 @@ import numpy as np
 from sympy import isprime
 
 __all__ = [
-    "rng", "limbs_for_bits", "find_prime", "uniform_residues", "to_ints",
+    "rng", "limbs_for_bits", "find_prime", "uniform_residues", "uniform_ints", "to_ints",
     "from_ints", "uniform_scalar", "Workload", "config_small", "config_paper",
-    "config_batched", "config_fused", "serving_stream", "PRIME_M",
+    "config_batched", "config_fused", "config_rns", "serving_stream", "PRIME_M",
 ]
 
 PRIME_M = 18  # q = 1 mod 2^18 for every seeded prime
