@@ -9,11 +9,12 @@
 // requests become complete and their scratch returns to the pool), then, while
 // a slot is free, admits requests from the head of the queue as long as their
 // memory fits and the batch has room, uploads the batch's descriptors with
-// asynchronous copies and launches it (transform / product requests through
+// one asynchronous copy and launches it (transform / product requests through
 // the batched executor, BLAS requests as their own kernels) on the slot's
 // stream.  Requests arriving meanwhile wait in the queue and go into the next
 // batch on the next free slot, so batches overlap on the device.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <atomic>
@@ -110,6 +111,22 @@ class Pool {
 
 enum ReqState { RQ_QUEUED, RQ_RUNNING, RQ_DONE, RQ_FAILED };
 
+// Byte offsets of the parts of a packed descriptor block, each 256-byte aligned.
+struct DescLayout {
+  size_t jobs = 0, m8 = 0, m4 = 0, m2 = 0, items = 0, items8 = 0, total = 0;
+};
+DescLayout desc_layout(size_t nj, size_t ni, size_t ni8) {
+  auto up = [](size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); };
+  DescLayout L;
+  L.m8 = up(sizeof(JobDesc) * nj);
+  L.m4 = L.m8 + up(sizeof(ModConst<8>) * nj);
+  L.m2 = L.m4 + up(sizeof(ModConst<4>) * nj);
+  L.items = L.m2 + up(sizeof(ModConst<2>) * nj);
+  L.items8 = L.items + up(sizeof(uint2) * ni);
+  L.total = L.items8 + sizeof(uint2) * ni8;
+  return L;
+}
+
 struct Req {
   mw_request r;
   size_t out_bytes = 0, scratch_bytes = 0;
@@ -122,18 +139,10 @@ struct Req {
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  JobDesc* d_jobs = nullptr;
-  uint2* d_items = nullptr;
-  uint2* d_items8 = nullptr;
-  ModConst<8>* d_m8 = nullptr;
-  ModConst<4>* d_m4 = nullptr;
-  ModConst<2>* d_m2 = nullptr;
-  JobDesc* h_jobs = nullptr;     // pinned staging
-  uint2* h_items = nullptr;
-  uint2* h_items8 = nullptr;
-  ModConst<8>* h_m8 = nullptr;
-  ModConst<4>* h_m4 = nullptr;
-  ModConst<2>* h_m2 = nullptr;
+  // A batch's descriptors (jobs, per-job constants, tile lists) packed into
+  // one block, staged in pinned memory and sent with a single copy.
+  char* d_desc = nullptr;
+  char* h_desc = nullptr;
   bool busy = false;
   double t_end = 0;              // dry run
   std::vector<uint64_t> tickets;
@@ -200,22 +209,20 @@ bool launch_batch(mw_server_s* S, Slot& slot, const std::vector<uint64_t>& batch
       return false;
     for (size_t i = 0; i < jobs.size(); ++i) plan.jobs[i].scratch = (u64)pool_ptr(S, S->reqs[job_tickets[i]].scratch_off);
     const size_t nj = plan.jobs.size(), ni = plan.items.size(), ni8 = plan.items8.size();
-    std::memcpy(slot.h_jobs, plan.jobs.data(), sizeof(JobDesc) * nj);
-    std::memcpy(slot.h_items, plan.items.data(), sizeof(uint2) * ni);
-    std::memcpy(slot.h_items8, plan.items8.data(), sizeof(uint2) * ni8);
-    std::memcpy(slot.h_m8, plan.m8.data(), sizeof(ModConst<8>) * nj);
-    std::memcpy(slot.h_m4, plan.m4.data(), sizeof(ModConst<4>) * nj);
-    std::memcpy(slot.h_m2, plan.m2.data(), sizeof(ModConst<2>) * nj);
-    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
-    if (hipMemcpyAsync(slot.d_jobs, slot.h_jobs, sizeof(JobDesc) * nj, h2d, slot.stream) != hipSuccess ||
-        (ni && hipMemcpyAsync(slot.d_items, slot.h_items, sizeof(uint2) * ni, h2d, slot.stream) != hipSuccess) ||
-        (ni8 && hipMemcpyAsync(slot.d_items8, slot.h_items8, sizeof(uint2) * ni8, h2d, slot.stream) != hipSuccess) ||
-        hipMemcpyAsync(slot.d_m8, slot.h_m8, sizeof(ModConst<8>) * nj, h2d, slot.stream) != hipSuccess ||
-        hipMemcpyAsync(slot.d_m4, slot.h_m4, sizeof(ModConst<4>) * nj, h2d, slot.stream) != hipSuccess ||
-        hipMemcpyAsync(slot.d_m2, slot.h_m2, sizeof(ModConst<2>) * nj, h2d, slot.stream) != hipSuccess)
+    const DescLayout L = desc_layout(nj, ni, ni8);
+    std::memcpy(slot.h_desc + L.jobs, plan.jobs.data(), sizeof(JobDesc) * nj);
+    std::memcpy(slot.h_desc + L.m8, plan.m8.data(), sizeof(ModConst<8>) * nj);
+    std::memcpy(slot.h_desc + L.m4, plan.m4.data(), sizeof(ModConst<4>) * nj);
+    std::memcpy(slot.h_desc + L.m2, plan.m2.data(), sizeof(ModConst<2>) * nj);
+    std::memcpy(slot.h_desc + L.items, plan.items.data(), sizeof(uint2) * ni);
+    std::memcpy(slot.h_desc + L.items8, plan.items8.data(), sizeof(uint2) * ni8);
+    if (hipMemcpyAsync(slot.d_desc, slot.h_desc, L.total, hipMemcpyHostToDevice, slot.stream) != hipSuccess)
       return false;
     if (exec_prepare(plan) != hipSuccess) return false;
-    const ExecDevice d{slot.d_jobs, slot.d_items, slot.d_items8, slot.d_m8, slot.d_m4, slot.d_m2};
+    char* b = slot.d_desc;
+    const ExecDevice d{(const JobDesc*)(b + L.jobs), (const uint2*)(b + L.items), (const uint2*)(b + L.items8),
+                       (const ModConst<8>*)(b + L.m8), (const ModConst<4>*)(b + L.m4),
+                       (const ModConst<2>*)(b + L.m2)};
     if (exec_launch(d, plan, slot.stream) != hipSuccess) return false;
   }
   for (uint64_t t : batch) {
@@ -231,6 +238,11 @@ bool launch_batch(mw_server_s* S, Slot& slot, const std::vector<uint64_t>& batch
 
 void scheduler(mw_server_s* S) {
   if (!S->cfg.dry_run) (void)hipSetDevice(S->device);
+  // While batches run the loop re-checks their events every few microseconds
+  // with a timed wait; Linux lets a timed wait overrun by the thread's timer
+  // slack (50 us by default), which would add that much to every request's
+  // latency.  1 us of slack keeps the polling interval what it says.
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
     bool progress = false;
@@ -360,18 +372,8 @@ void free_server(mw_server_s* S) {
   for (Slot& s : S->slots) {
     if (s.stream) (void)hipStreamDestroy(s.stream);
     if (s.done) (void)hipEventDestroy(s.done);
-    if (s.d_jobs) (void)hipFree(s.d_jobs);
-    if (s.d_items) (void)hipFree(s.d_items);
-    if (s.d_items8) (void)hipFree(s.d_items8);
-    if (s.d_m8) (void)hipFree(s.d_m8);
-    if (s.d_m4) (void)hipFree(s.d_m4);
-    if (s.d_m2) (void)hipFree(s.d_m2);
-    if (s.h_jobs) (void)hipHostFree(s.h_jobs);
-    if (s.h_items) (void)hipHostFree(s.h_items);
-    if (s.h_items8) (void)hipHostFree(s.h_items8);
-    if (s.h_m8) (void)hipHostFree(s.h_m8);
-    if (s.h_m4) (void)hipHostFree(s.h_m4);
-    if (s.h_m2) (void)hipHostFree(s.h_m2);
+    if (s.d_desc) (void)hipFree(s.d_desc);
+    if (s.h_desc) (void)hipHostFree(s.h_desc);
   }
   if (S->pool_base) (void)hipFree(S->pool_base);
   delete S;
@@ -394,7 +396,8 @@ extern "C" int mw_server_create(mw_server_t* out, const mw_server_config* cfg) {
     int st = MW_OK;
     if (hipGetDevice(&S->device) != hipSuccess) st = MW_EDEVICE;
     if (st == MW_OK && hipMalloc(&S->pool_base, S->pool.size()) != hipSuccess) st = MW_ENOMEM;
-    const size_t nj = cfg->max_batch, ni = (size_t)cfg->max_batch * kMaxTilesPerJob;
+    const size_t ni = (size_t)cfg->max_batch * kMaxTilesPerJob;
+    const size_t cap = desc_layout(cfg->max_batch, ni, ni).total;
     for (Slot& s : S->slots) {
       if (st != MW_OK) break;
       if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -402,18 +405,7 @@ extern "C" int mw_server_create(mw_server_t* out, const mw_server_config* cfg) {
         st = MW_EDEVICE;
         break;
       }
-      if (hipMalloc(&s.d_jobs, sizeof(JobDesc) * nj) != hipSuccess ||
-          hipMalloc(&s.d_items, sizeof(uint2) * ni) != hipSuccess ||
-          hipMalloc(&s.d_items8, sizeof(uint2) * ni) != hipSuccess ||
-          hipMalloc(&s.d_m8, sizeof(ModConst<8>) * nj) != hipSuccess ||
-          hipMalloc(&s.d_m4, sizeof(ModConst<4>) * nj) != hipSuccess ||
-          hipMalloc(&s.d_m2, sizeof(ModConst<2>) * nj) != hipSuccess ||
-          hipHostMalloc(&s.h_jobs, sizeof(JobDesc) * nj) != hipSuccess ||
-          hipHostMalloc(&s.h_items, sizeof(uint2) * ni) != hipSuccess ||
-          hipHostMalloc(&s.h_items8, sizeof(uint2) * ni) != hipSuccess ||
-          hipHostMalloc(&s.h_m8, sizeof(ModConst<8>) * nj) != hipSuccess ||
-          hipHostMalloc(&s.h_m4, sizeof(ModConst<4>) * nj) != hipSuccess ||
-          hipHostMalloc(&s.h_m2, sizeof(ModConst<2>) * nj) != hipSuccess)
+      if (hipMalloc(&s.d_desc, cap) != hipSuccess || hipHostMalloc(&s.h_desc, cap) != hipSuccess)
         st = MW_ENOMEM;
     }
     if (st != MW_OK) {
