@@ -124,7 +124,7 @@ def time_graph(fn, stream, reps=20):
     return us
 
 
-def serving_leg(count, rate=20000.0, budget=1 << 30):
+def serving_leg(count, rate=20000.0, budget=1 << 30, spin_us=0):
     """Open-loop Poisson stream through the serving runtime (inputs pre-staged).
 
     70% transforms (half forward, half inverse) with N = 2^e, e uniform in
@@ -159,7 +159,7 @@ def serving_leg(count, rate=20000.0, budget=1 << 30):
         arrivals.append(j["t"] * 1e6)
     torch.cuda.synchronize()
     progress(f"serving: {len(plans)} plans, {len(bufs)} input buffers staged")
-    srv = mwntt.MwServer(budget, max_inflight=4, max_batch=64)
+    srv = mwntt.MwServer(budget, max_inflight=4, max_batch=64, spin_us=spin_us)
     warm = min(2000, count)
     srv.replay(reqs[:warm], [a - arrivals[0] for a in arrivals[:warm]])
     lat, span = srv.replay(reqs, arrivals)
@@ -167,7 +167,7 @@ def serving_leg(count, rate=20000.0, budget=1 << 30):
     srv.destroy()
     for p in plans.values():
         p.destroy()
-    return {"requests": count, "offered_rate": rate, "hbm_budget": budget,
+    return {"requests": count, "offered_rate": rate, "hbm_budget": budget, "spin_us": spin_us,
             "throughput_req_s": round(count / (span * 1e-6), 1),
             "p50_us": round(percentile(lat, 50), 2), "p99_us": round(percentile(lat, 99), 2),
             "mean_us": round(sum(lat) / len(lat), 2), "makespan_s": round(span * 1e-6, 4),

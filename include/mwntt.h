@@ -185,7 +185,8 @@ typedef struct {
  * batch, and the job buffers must stay allocated at the same addresses for
  * every run. */
 int ntt_batch_create(ntt_batch_t* batch, const ntt_job* jobs, uint32_t count);
-/* Runs every job: 2 or 3 kernel launches on `stream`, no allocation and no
+/* Runs every job: 2 or 3 kernel launches on `stream` (twice that with
+ * four-word jobs in the batch), no allocation and no
  * memset, so a run can be captured in a hipGraph and replayed.  Runs of one
  * batch must not overlap in time (they share the batch's scratch). */
 int ntt_batch_run(ntt_batch_t batch, void* stream);
@@ -220,6 +221,12 @@ typedef struct {
   uint32_t dry_run;       /* 1: scheduler only, no device memory or work; every
                              request completes after a modelled time and has no
                              output (for testing admission and queueing) */
+  uint32_t spin_us;       /* 0: the scheduler thread sleeps whenever it has
+                             nothing to do (woken by submissions, polling
+                             running batches every few microseconds); n > 0:
+                             it keeps polling without sleeping for n
+                             microseconds after its last action, 0 .. 100000
+                             (lower latency for one busy host core) */
 } mw_server_config;
 
 enum mw_request_op {

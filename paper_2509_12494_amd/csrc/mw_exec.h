@@ -60,6 +60,9 @@ struct ExecPlan {
   std::vector<size_t> scratch_bytes;
   u32 phase_begin[4] = {0, 0, 0, 0};
   u32 phase_begin8[4] = {0, 0, 0, 0};
+  // per phase, the limb counts (bit `limbs`) present in `items`: a phase with
+  // one width runs that width's kernel, a phase with both the kernel for both
+  u32 phase_widths[3] = {0, 0, 0};
   u32 nphases = 0;
   size_t phase_lds[3] = {0, 0, 0};
   size_t phase_lds8[3] = {0, 0, 0};

@@ -17,9 +17,16 @@
 // waits for tiles on other XCDs must write back and invalidate L2 around every
 // hand-off, which costs more than the launch it would save.
 //
-// The tiles run the run-time line engine of mw_ntt_rt.h with 4 points per
-// lane for two-word moduli, 8 for one-word and 2 for four-word moduli (the
-// shapes the autotuner found best for batches), 256 lanes per workgroup.
+// Tiles have 256 lanes and 4 points per lane for two-word moduli, 8 for
+// one-word and 2 for four-word moduli (the shapes the autotuner found best for
+// batches).  A launch whose tiles all have one width runs a kernel of that
+// width only, in which tiles whose lines fill the 256 lanes (transforms of
+// 2^(8 + log2 points per lane) points and more) with a line length of
+// 2^5 .. 2^9 run the tile code of the single-purpose kernels, specialised per
+// line length; the other tiles, and every tile of a launch that mixes one-
+// and two-word moduli, run the run-time line engine of mw_ntt_rt.h (one
+// kernel holding the specialised tiles of both widths needs more registers
+// than either alone, and spills).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,7 +39,32 @@
 
 namespace mw {
 
-template <int W, int LOGP>
+// Line lengths 2^5 .. 2^9 get the compile-time tile code.
+constexpr u32 kFixedLogLMin = 5, kFixedLogLMax = 9;
+
+// One column or row tile.  With FIXED, a tile whose lines fill the workgroup
+// (lines * 2^(logl - LOGP) == kExecThreads, no idle lanes) and whose line
+// length has compile-time code runs the tile code of the single-purpose
+// kernels (stage loops unrolled, indices constant); any other tile the
+// run-time line engine.
+template <int W, int LOGP, int DIR, int MODE, bool FIXED>
+__device__ __forceinline__ void run_tile(const NttParams<W>& p, Res<W>* lds, u32 tile) {
+  if constexpr (FIXED) {
+    const u32 logl = MODE == MODE_COL ? p.log_n1 : p.log_n - p.log_n1;
+    if (logl >= kFixedLogLMin && logl <= kFixedLogLMax && (p.lines << (logl - LOGP)) == kExecThreads) {
+      switch (logl) {
+        case 5: if constexpr (shape_ok<W, MODE>(5, LOGP)) ntt_tile<W, 5, LOGP, DIR, MODE>(p, lds, tile); return;
+        case 6: if constexpr (shape_ok<W, MODE>(6, LOGP)) ntt_tile<W, 6, LOGP, DIR, MODE>(p, lds, tile); return;
+        case 7: if constexpr (shape_ok<W, MODE>(7, LOGP)) ntt_tile<W, 7, LOGP, DIR, MODE>(p, lds, tile); return;
+        case 8: if constexpr (shape_ok<W, MODE>(8, LOGP)) ntt_tile<W, 8, LOGP, DIR, MODE>(p, lds, tile); return;
+        default: if constexpr (shape_ok<W, MODE>(9, LOGP)) ntt_tile<W, 9, LOGP, DIR, MODE>(p, lds, tile); return;
+      }
+    }
+  }
+  rt_tile<W, LOGP, DIR, MODE>(p, lds, tile);
+}
+
+template <int W, int LOGP, bool FIXED>
 __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J, u32 job, u32 phase, u32 tile,
                                          unsigned char* smem) {
   const ModConst<W>* mc;
@@ -59,19 +91,19 @@ __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J,
     p.tw = twf;
     if (phase == 0) {
       p.src = in; p.dst = scr; p.lines = J.lines_col;
-      rt_tile<W, LOGP, DIR_FWD, MODE_COL>(p, lds, tile);
+      run_tile<W, LOGP, DIR_FWD, MODE_COL, FIXED>(p, lds, tile);
     } else {
       p.src = scr; p.dst = out; p.lines = J.lines_row; p.permute = J.perm_out;
-      rt_tile<W, LOGP, DIR_FWD, MODE_ROW>(p, lds, tile);
+      run_tile<W, LOGP, DIR_FWD, MODE_ROW, FIXED>(p, lds, tile);
     }
   } else if (J.op == JOB_INV) {
     p.tw = twi;
     if (phase == 0) {
       p.src = in; p.dst = scr; p.lines = J.lines_row; p.permute = J.perm_in;
-      rt_tile<W, LOGP, DIR_INV, MODE_ROW>(p, lds, tile);
+      run_tile<W, LOGP, DIR_INV, MODE_ROW, FIXED>(p, lds, tile);
     } else {
       p.src = scr; p.dst = out; p.lines = J.lines_col;
-      rt_tile<W, LOGP, DIR_INV, MODE_COL>(p, lds, tile);
+      run_tile<W, LOGP, DIR_INV, MODE_COL, FIXED>(p, lds, tile);
     }
   } else {
     const u32 ncol = J.tiles[2];
@@ -80,7 +112,7 @@ __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J,
       const bool second = tile >= ncol;
       p.src = second ? in2 : in;
       p.dst = second ? scr + N : scr;
-      rt_tile<W, LOGP, DIR_FWD, MODE_COL>(p, lds, second ? tile - ncol : tile);
+      run_tile<W, LOGP, DIR_FWD, MODE_COL, FIXED>(p, lds, second ? tile - ncol : tile);
     } else if (phase == 1) {
       NttParams<W> pi = p;
       p.tw = twf; p.lines = J.lines_row; p.src = scr; p.dst = scr;
@@ -88,30 +120,34 @@ __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J,
       rt_fused_row<W, LOGP>(p, pi, scr + N, lds, tile);
     } else {
       p.tw = twi; p.lines = J.lines_col; p.src = scr; p.dst = out;
-      rt_tile<W, LOGP, DIR_INV, MODE_COL>(p, lds, tile);
+      run_tile<W, LOGP, DIR_INV, MODE_COL, FIXED>(p, lds, tile);
     }
   }
 }
 
+// Tiles of one- and two-word jobs; item {job | limbs << 16, phase << 16 | tile}.
+// The width comes with the item, so the job descriptor and the modulus
+// constants (both indexed by the job) load in parallel instead of one after
+// the other.  Run-time line engine only (launches that mix the two widths).
 __global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(4))) void exec_kernel(ExecParams ep) {
   extern __shared__ __align__(16) unsigned char mw_exec_smem[];
-  // item: {job | limbs << 16, phase << 16 | tile}.  The width comes with the
-  // item, so the job descriptor and the modulus constants (both indexed by
-  // the job) load in parallel instead of one after the other.
   const uint2 it = ep.items[blockIdx.x];
   const u32 job = it.x & 0xffffu, limbs = it.x >> 16, phase = it.y >> 16, tile = it.y & 0xffffu;
   const JobDesc J = ep.jobs[job];
-  if (limbs == 2) run_item<4, kLogP4>(ep, J, job, phase, tile, mw_exec_smem);
-  else run_item<2, kLogP2>(ep, J, job, phase, tile, mw_exec_smem);
+  if (limbs == 2) run_item<4, kLogP4, false>(ep, J, job, phase, tile, mw_exec_smem);
+  else run_item<2, kLogP2, false>(ep, J, job, phase, tile, mw_exec_smem);
 }
 
-// The tiles of four-word jobs (their own launch: see ExecPlan).
-__global__ __launch_bounds__(kExecThreads) void exec_kernel8(ExecParams ep) {
+// Tiles of one width (W 32-bit words per residue), with the specialised tile
+// code; four-word jobs always run here (their own launch: see ExecPlan).
+template <int W>
+__global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(4))) void exec_kernel_w(ExecParams ep) {
   extern __shared__ __align__(16) unsigned char mw_exec_smem[];
   const uint2 it = ep.items[blockIdx.x];
   const u32 job = it.x & 0xffffu, phase = it.y >> 16, tile = it.y & 0xffffu;
   const JobDesc J = ep.jobs[job];
-  run_item<8, kLogP8>(ep, J, job, phase, tile, mw_exec_smem);
+  constexpr int LOGP = W == 8 ? kLogP8 : (W == 4 ? kLogP4 : kLogP2);
+  run_item<W, LOGP, true>(ep, J, job, phase, tile, mw_exec_smem);
 }
 
 // host twin of xcd_tile: the tile that position b of a run of n tiles takes
@@ -208,6 +244,7 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
         const u32 t = col ? xcd_order(b, n) : b;
         list.push_back(make_uint2(i | (d.limbs << 16), (ph << 16) | t));
       }
+      if (n && d.limbs != 4) out.phase_widths[ph] |= 1u << d.limbs;
     }
     if (out.items.size() > out.phase_begin[ph] || out.items8.size() > out.phase_begin8[ph]) out.nphases = ph + 1;
   }
@@ -216,17 +253,28 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
   return MW_OK;
 }
 
+template <typename K>
+static hipError_t raise_lds(K kernel, size_t lds) {
+  if (lds <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             160 * 1024);
+}
+
 hipError_t exec_prepare(const ExecPlan& plan) {
   const size_t lds = std::max(plan.phase_lds[0], std::max(plan.phase_lds[1], plan.phase_lds[2]));
   const size_t lds8 = std::max(plan.phase_lds8[0], std::max(plan.phase_lds8[1], plan.phase_lds8[2]));
+  // once per kernel: the first run that needs the larger limit raises it
   if (lds > 65536) {
-    static const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(exec_kernel),
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    static const hipError_t e = [] {
+      hipError_t r = raise_lds(exec_kernel, 65537);
+      if (r == hipSuccess) r = raise_lds(exec_kernel_w<2>, 65537);
+      if (r == hipSuccess) r = raise_lds(exec_kernel_w<4>, 65537);
+      return r;
+    }();
     if (e != hipSuccess) return e;
   }
   if (lds8 > 65536) {
-    static const hipError_t e8 = hipFuncSetAttribute(reinterpret_cast<const void*>(exec_kernel8),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    static const hipError_t e8 = raise_lds(exec_kernel_w<8>, 65537);
     if (e8 != hipSuccess) return e8;
   }
   return hipSuccess;
@@ -242,14 +290,18 @@ hipError_t exec_launch(const ExecDevice& d, const ExecPlan& plan, hipStream_t s)
     const u32 n = plan.phase_begin[k + 1] - plan.phase_begin[k];
     if (n) {
       ep.items = d.items + plan.phase_begin[k];
-      hipLaunchKernelGGL(exec_kernel, dim3(n), dim3(kExecThreads), plan.phase_lds[k], s, ep);
+      const size_t lds = plan.phase_lds[k];
+      const u32 widths = plan.phase_widths[k];
+      if (widths == (1u << 2)) hipLaunchKernelGGL(exec_kernel_w<4>, dim3(n), dim3(kExecThreads), lds, s, ep);
+      else if (widths == (1u << 1)) hipLaunchKernelGGL(exec_kernel_w<2>, dim3(n), dim3(kExecThreads), lds, s, ep);
+      else hipLaunchKernelGGL(exec_kernel, dim3(n), dim3(kExecThreads), lds, s, ep);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     const u32 n8 = plan.phase_begin8[k + 1] - plan.phase_begin8[k];
     if (n8) {
       ep.items = d.items8 + plan.phase_begin8[k];
-      hipLaunchKernelGGL(exec_kernel8, dim3(n8), dim3(kExecThreads), plan.phase_lds8[k], s, ep);
+      hipLaunchKernelGGL(exec_kernel_w<8>, dim3(n8), dim3(kExecThreads), plan.phase_lds8[k], s, ep);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }

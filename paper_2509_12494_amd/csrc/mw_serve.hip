@@ -244,6 +244,7 @@ void scheduler(mw_server_s* S) {
   // latency.  1 us of slack keeps the polling interval what it says.
   (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(S->mu);
+  double last_action = now_us();
   for (;;) {
     bool progress = false;
     // retire finished batches
@@ -324,7 +325,14 @@ void scheduler(mw_server_s* S) {
       progress = true;
     }
     if (S->stop && S->queue.empty() && S->inflight == 0) break;
-    if (!progress) {
+    if (progress) {
+      last_action = now_us();
+    } else if (S->cfg.spin_us && now_us() - last_action < S->cfg.spin_us) {
+      // busy polling: let submitters take the lock, then look again
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    } else {
       // poll completions often while batches run, otherwise sleep until work
       if (S->inflight) S->cv_work.wait_for(lk, std::chrono::microseconds(4));
       else S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
@@ -385,7 +393,7 @@ extern "C" int mw_server_create(mw_server_t* out, const mw_server_config* cfg) {
   if (!out || !cfg) return MW_EINVAL;
   *out = nullptr;
   if (cfg->max_inflight < 1 || cfg->max_inflight > 16 || cfg->max_batch < 1 || cfg->max_batch > kMaxBatch ||
-      cfg->hbm_budget < kAlign)
+      cfg->hbm_budget < kAlign || cfg->spin_us > 100000)
     return MW_EINVAL;
   mw_server_s* S = new (std::nothrow) mw_server_s();
   if (!S) return MW_ENOMEM;

@@ -245,7 +245,9 @@ def test_three_widths_in_one_batch():
     batch = mwntt.NttBatch(jobs)
     info = batch.info()
     announce("batch three widths", info)
-    assert info["launches"] > 3   # phases with four-word tiles take a second launch
+    # one launch per phase for the one- and two-word tiles (products present:
+    # three phases) and one per phase for the four-word tiles (no product: two)
+    assert info["launches"] == 3 + 2
     for rep in range(2):
         for out, _, _ in checks:
             out.zero_()
@@ -344,6 +346,65 @@ def test_random_mixes_match_plain(seed):
             else:
                 src = a_i
                 if flags & mwntt.NTT_BITREV_IN:     # input is a spectrum in bit-reversed order
+                    src = [a_i[bitrev(k, plan.log2n)] for k in range(n)]
+                assert [got[k] for k in ks] == oracle.ntt.inverse_at(src, q, ks)
+    batch.destroy()
+    for plan, *_ in refs:
+        plan.destroy()
+
+
+@pytest.mark.parametrize("bits", [60, 124, 252])
+def test_single_width_batches_match_plain(bits):
+    """A batch of one modulus width runs that width's kernel, whose tiles of
+    2^5 .. 2^9-point lines have compile-time code: forward (natural and
+    bit-reversed output), inverse (natural and bit-reversed input) and
+    products for N = 2^8 .. 2^17, every output equal to the plain entry
+    points, sampled outputs to the oracle."""
+    require_gpu()
+    import torch
+    limbs = W.limbs_for_bits(bits)
+    g = W.rng(9300 + bits)
+    jobs, refs = [], []
+    for log2n in range(8, 18):
+        for op in (mwntt.NTT_JOB_FORWARD, mwntt.NTT_JOB_INVERSE, mwntt.NTT_JOB_POLYMUL):
+            if op == mwntt.NTT_JOB_POLYMUL and bits == 252 and log2n > 15:
+                continue   # keeps the four-word case within the test's time
+            flags = 0
+            if op == mwntt.NTT_JOB_FORWARD and log2n % 2:
+                flags = mwntt.NTT_BITREV_OUT
+            if op == mwntt.NTT_JOB_INVERSE and log2n % 2 == 0:
+                flags = mwntt.NTT_BITREV_IN
+            q = prime(bits, 60 + log2n % 2)
+            plan = mwntt.ntt_plan(log2n, q, limbs, flags=flags)
+            n = plan.n
+            A, B = W.uniform_residues(g, q, n, limbs), W.uniform_residues(g, q, n, limbs)
+            a, b = dev(A), dev(B)
+            out = torch.empty_like(a)
+            jobs.append((plan, op, a, b if op == mwntt.NTT_JOB_POLYMUL else None, out))
+            refs.append((plan, op, a, b, out, A, B, flags))
+    batch = mwntt.NttBatch(jobs)
+    info = batch.info()
+    announce("single width", bits, info)
+    assert info["launches"] == 3          # one width: one launch per phase
+    batch.run()
+    batch.check()
+    for i, (plan, op, a, b, out, A, B, flags) in enumerate(refs):
+        want = _plain(plan, op, a, b)
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), f"job {i}: op {op}, N {plan.n}, flags {flags}"
+        if i % 4 == 0:
+            n, q = plan.n, plan.q
+            ks = [0, n - 1, (i * 977) % n]
+            got = host_ints(out, plan.limbs)
+            a_i, b_i = W.to_ints(A), W.to_ints(B)
+            if op == mwntt.NTT_JOB_POLYMUL:
+                assert [got[k] for k in ks] == oracle.polymul.negacyclic_at(a_i, b_i, q, ks)
+            elif op == mwntt.NTT_JOB_FORWARD:
+                pos = [bitrev(k, plan.log2n) if flags & mwntt.NTT_BITREV_OUT else k for k in ks]
+                assert [got[p_] for p_ in pos] == oracle.ntt.forward_at(a_i, q, ks)
+            else:
+                src = a_i
+                if flags & mwntt.NTT_BITREV_IN:
                     src = [a_i[bitrev(k, plan.log2n)] for k in range(n)]
                 assert [got[k] for k in ks] == oracle.ntt.inverse_at(src, q, ks)
     batch.destroy()

@@ -120,3 +120,17 @@ def test_config_errors():
         mwntt.MwServer(1 << 20, max_inflight=0, dry_run=True)
     with pytest.raises(mwntt.MwError):
         mwntt.MwServer(1 << 20, max_batch=1000, dry_run=True)
+    with pytest.raises(mwntt.MwError):
+        mwntt.MwServer(1 << 20, spin_us=200000, dry_run=True)
+
+
+def test_spinning_scheduler_completes_stream():
+    # a scheduler that polls without sleeping between actions serves the same
+    # requests as a sleeping one
+    reqs = [_req(1024 + 37 * i) for i in range(300)]
+    arrivals = [20.0 * i for i in range(300)]
+    srv = mwntt.MwServer(1 << 24, max_inflight=2, max_batch=8, dry_run=True, spin_us=500)
+    lat, span = srv.replay(reqs, arrivals)
+    assert len(lat) == 300 and min(lat) >= 0 and span >= arrivals[-1]
+    assert srv.stats()["completed"] == 300
+    srv.destroy()
