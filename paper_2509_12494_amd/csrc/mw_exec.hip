@@ -64,6 +64,80 @@ __device__ __forceinline__ void run_tile(const NttParams<W>& p, Res<W>* lds, u32
   rt_tile<W, LOGP, DIR, MODE>(p, lds, tile);
 }
 
+// Fused row tile of a product with the line length fixed at compile time and
+// lines * L/P == kExecThreads: the steps of rt_fused_row (the last forward
+// stages of a and of b on `lines` consecutive rows, their point-wise Barrett
+// product, the first inverse stages, written back over a's rows) with every
+// lane busy and every shift and stage count constant.
+template <int W, int LOGP, int LOGL>
+__device__ __forceinline__ void fixed_fused_row(const NttParams<W>& pf, const NttParams<W>& pi, const Res<W>* src2,
+                                                Res<W>* lds, u32 tile) {
+  using S = LineShape<LOGL, LOGP>;
+  constexpr u32 L = S::L;
+  constexpr int P = S::P;
+  constexpr u32 lines = kExecThreads / S::TPL;
+  const u32 t = threadIdx.x;
+  const u32 line_id = t / S::TPL, lane = t % S::TPL;
+  const u32 row0 = tile * lines;
+  Res<W>* la = lds;
+  Res<W>* lb = lds + lines * S::NPAD;
+  const auto off = [&](u32 e) { return ((u64)(row0 + e / L) << LOGL) + (e & (L - 1)); };
+  const auto slot = [&](u32 e) { return (e / L) * S::NPAD + pad_idx<LOGL, LOGP>(e & (L - 1)); };
+  {
+    // all 2P loads of a and b in flight before the first LDS write
+    Res<W> va[P], vb[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const u32 e = t + (u32)k * kExecThreads;
+      va[k] = ResIO<W>::load(pf.src + off(e));
+      vb[k] = ResIO<W>::load(src2 + off(e));
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const u32 e = t + (u32)k * kExecThreads;
+      la[slot(e)] = va[k];
+      lb[slot(e)] = vb[k];
+    }
+  }
+  __syncthreads();
+  const u32 base = (1u << pf.log_n1) + row0 + line_id;
+  line_stages<W, LOGL, LOGP, DIR_FWD>(la + line_id * S::NPAD, lane, base, pf.tw, pf, false, true);
+  line_stages<W, LOGL, LOGP, DIR_FWD>(lb + line_id * S::NPAD, lane, base, pf.tw, pf, false, true);
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const u32 idx = slot(t + (u32)k * kExecThreads);
+    la[idx] = barrett_mul(la[idx], lb[idx], pf.M);
+  }
+  __syncthreads();
+  line_stages<W, LOGL, LOGP, DIR_INV>(la + line_id * S::NPAD, lane, base, pi.tw, pi, false, false);
+  const auto all = [](u32) { return true; };
+  copy_staged<W, P>(
+      t, kExecThreads, all, [&](u32 e) { return la[slot(e)]; },
+      [&](u32 e, const Res<W>& v) { ResIO<W>::store(pf.dst + off(e), v); });
+}
+
+// The fused row tile of a product: with FIXED and a tile that fills the
+// workgroup, the compile-time version -- for two-word moduli only: with the
+// one- and four-word kernels' other tiles it exceeds their registers and
+// spills.
+template <int W, int LOGP, bool FIXED>
+__device__ __forceinline__ void run_fused_row(const NttParams<W>& pf, const NttParams<W>& pi, const Res<W>* src2,
+                                              Res<W>* lds, u32 tile) {
+  if constexpr (FIXED && W == 4) {
+    const u32 logl = pf.log_n - pf.log_n1;
+    if (logl >= kFixedLogLMin && logl <= kFixedLogLMax && (pf.lines << (logl - LOGP)) == kExecThreads) {
+      switch (logl) {
+        case 5: if constexpr (shape_ok<W, MODE_ROW>(5, LOGP)) fixed_fused_row<W, LOGP, 5>(pf, pi, src2, lds, tile); return;
+        case 6: if constexpr (shape_ok<W, MODE_ROW>(6, LOGP)) fixed_fused_row<W, LOGP, 6>(pf, pi, src2, lds, tile); return;
+        case 7: if constexpr (shape_ok<W, MODE_ROW>(7, LOGP)) fixed_fused_row<W, LOGP, 7>(pf, pi, src2, lds, tile); return;
+        case 8: if constexpr (shape_ok<W, MODE_ROW>(8, LOGP)) fixed_fused_row<W, LOGP, 8>(pf, pi, src2, lds, tile); return;
+        default: if constexpr (shape_ok<W, MODE_ROW>(9, LOGP)) fixed_fused_row<W, LOGP, 9>(pf, pi, src2, lds, tile); return;
+      }
+    }
+  }
+  rt_fused_row<W, LOGP>(pf, pi, src2, lds, tile);
+}
+
 template <int W, int LOGP, bool FIXED>
 __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J, u32 job, u32 phase, u32 tile,
                                          unsigned char* smem) {
@@ -117,7 +191,7 @@ __device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J,
       NttParams<W> pi = p;
       p.tw = twf; p.lines = J.lines_row; p.src = scr; p.dst = scr;
       pi.tw = twi; pi.lines = J.lines_row;
-      rt_fused_row<W, LOGP>(p, pi, scr + N, lds, tile);
+      run_fused_row<W, LOGP, FIXED>(p, pi, scr + N, lds, tile);
     } else {
       p.tw = twi; p.lines = J.lines_col; p.src = scr; p.dst = out;
       run_tile<W, LOGP, DIR_INV, MODE_COL, FIXED>(p, lds, tile);
