@@ -15,7 +15,8 @@ op's stream); algorithmic Gmulmod/s; the batched (96 transforms per call)
 rate; ``legs``: the executor on the same batch, a batch sweep, a
 host-inclusive (pinned copies in and out) figure, the mixed 96-polynomial
 batch and its inverse, 256 fused products at 2^14, RNS products over eight
-primes, the 252-bit transform and BLAS, and the serving replay; the roofline
+primes, the 252-bit transform and BLAS, BLAS at streaming sizes (2^24) against
+the HBM peak, and the serving replay; the roofline
 of the dominant kernel (with HBM traffic and VALU instructions from the
 committed rocprofv3 summary); and the CPU oracle's rate on a bounded sample.
 """
@@ -465,6 +466,32 @@ def main():
     legs["wide_252bit_2e16"] = wide
     wplan.destroy()
     del wx, wy, wz
+
+    # BLAS at streaming sizes: n = 2^24 residues (2^23 for 252-bit), inputs
+    # resident; algorithmic bytes = two vectors read + one written
+    progress("BLAS streaming leg")
+    stream_leg = {}
+    for bits, lg in ((60, 24), (124, 24), (252, 23)):
+        qs = W.find_prime(bits, 2001)
+        ls = W.limbs_for_bits(bits)
+        ns = 1 << lg
+        sa = mwntt.to_device(W.uniform_residues(W.rng(7700 + bits), qs, ns, ls))
+        sb = torch.roll(sa, 1, 0)                      # a permutation of the same uniform residues
+        sc = torch.empty_like(sa)
+        alpha_s = (qs - 1) // 3
+        nbytes = 3 * ns * 8 * ls
+        row = {"n": ns}
+        for nm, f in (("add", lambda: mwntt.vec_addmod(sc, sa, sb, qs, ls, stream=sp)),
+                      ("mul", lambda: mwntt.vec_mulmod(sc, sa, sb, qs, ls, stream=sp)),
+                      ("axpy", lambda: mwntt.vec_axpymod(sc, alpha_s, sa, qs, ls, stream=sp))):
+            us = time_calls(f, stream, reps=20)
+            gbs = nbytes / (us * 1e-6) / 1e9
+            row[nm] = {"us": round(us, 1), "GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 3)}
+            if nm == "mul":
+                row[nm]["gmulmod_s"] = round(ns / (us * 1e-6) / 1e9, 2)
+        stream_leg[f"{bits}bit"] = row
+        del sa, sb, sc
+    legs["blas_stream"] = stream_leg
 
     if args.serve_requests:
         progress(f"serving leg: {args.serve_requests} requests")

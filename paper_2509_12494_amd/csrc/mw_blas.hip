@@ -7,6 +7,13 @@
 // residues with 16-byte vector loads; a grid-stride loop over chunks of
 // VEC*blockDim residues keeps the grid at a few waves per SIMD for any length,
 // and a guarded scalar path handles the ragged tail.
+//
+// Cache policy of the streamed accesses (measured on MI355X at n = 2^24,
+// algorithmic bytes: two vectors in, one out): one-word residues store with
+// the non-temporal hint (5.4-5.5 -> 6.5-6.9 TB/s), two-word residues load and
+// store with it (5.3-5.5 -> 5.7-6.1 TB/s); four-word residues, read as two
+// 16-byte halves per lane, are fastest with ordinary accesses (every
+// non-temporal form lost 3-19% there).
 #include <hip/hip_runtime.h>
 
 #include "mw_arith.h"
@@ -41,6 +48,38 @@ __device__ __forceinline__ Res<W> blas_elem(const Res<W>& a, const Res<W>& b, co
   }
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Loads and stores of the main streaming loop, per width (see the cache
+// policy above).
+template <int W>
+struct Stream {
+  __device__ static __forceinline__ Res<W> load(const Res<W>* p) { return ResIO<W>::load(p); }
+  __device__ static __forceinline__ void store(Res<W>* p, const Res<W>& r) { ResIO<W>::store(p, r); }
+};
+template <>
+struct Stream<2> {
+  __device__ static __forceinline__ Res<2> load(const Res<2>* p) { return ResIO<2>::load(p); }
+  __device__ static __forceinline__ void store(Res<2>* p, const Res<2>& r) {
+    const u32x2 v = {r.v[0], r.v[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x2*>(p));
+  }
+};
+template <>
+struct Stream<4> {
+  __device__ static __forceinline__ Res<4> load(const Res<4>* p) {
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+    Res<4> r;
+    r.v[0] = v.x; r.v[1] = v.y; r.v[2] = v.z; r.v[3] = v.w;
+    return r;
+  }
+  __device__ static __forceinline__ void store(Res<4>* p, const Res<4>& r) {
+    const u32x4 v = {r.v[0], r.v[1], r.v[2], r.v[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(p));
+  }
+};
+
 template <int W, int OP, int VEC>
 __global__ __launch_bounds__(256) void blas_kernel(Res<W>* c, const Res<W>* a,
                                                    const Res<W>* b, u64 n, Modulus<W> M,
@@ -52,11 +91,11 @@ __global__ __launch_bounds__(256) void blas_kernel(Res<W>* c, const Res<W>* a,
     Res<W> x[VEC], y[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
-      x[v] = ResIO<W>::load(a + base + (u64)v * blockDim.x);
-      y[v] = ResIO<W>::load(b + base + (u64)v * blockDim.x);
+      x[v] = Stream<W>::load(a + base + (u64)v * blockDim.x);
+      y[v] = Stream<W>::load(b + base + (u64)v * blockDim.x);
     }
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) ResIO<W>::store(c + base + (u64)v * blockDim.x, blas_elem<W, OP>(x[v], y[v], M, s));
+    for (int v = 0; v < VEC; ++v) Stream<W>::store(c + base + (u64)v * blockDim.x, blas_elem<W, OP>(x[v], y[v], M, s));
   }
   // ragged tail: residues [nfull*chunk, n), handled by the one block whose
   // turn comes next in the grid-stride order
