@@ -98,15 +98,17 @@ def _oracle_sample(it, ks):
     return [(it["alpha"] * a[k] + b[k]) % q for k in ks]
 
 
-@pytest.mark.parametrize("budget,inflight,batch,wide", [(1 << 30, 1, 32, False), (1 << 30, 4, 32, False),
-                                                        (3 << 20, 2, 4, False), (1 << 30, 3, 16, True)])
-def test_mixed_stream_matches_alone(budget, inflight, batch, wide):
-    """wide: 60-, 124- and 252-bit requests in one stream."""
+@pytest.mark.parametrize("budget,inflight,batch,wide,spin", [(1 << 30, 1, 32, False, 0), (1 << 30, 4, 32, False, 0),
+                                                             (3 << 20, 2, 4, False, 0), (1 << 30, 3, 16, True, 0),
+                                                             (1 << 30, 2, 8, False, 500)])
+def test_mixed_stream_matches_alone(budget, inflight, batch, wide, spin):
+    """wide: 60-, 124- and 252-bit requests in one stream; spin: the scheduler
+    polls without sleeping for that many microseconds after each action."""
     require_gpu()
     import torch
     items, plans = _workload(56, seed=budget % 1000 + inflight, wide=wide)
-    srv = mwntt.MwServer(budget, max_inflight=inflight, max_batch=batch)
-    announce("serve mixed", budget, inflight, batch)
+    srv = mwntt.MwServer(budget, max_inflight=inflight, max_batch=batch, spin_us=spin)
+    announce("serve mixed", budget, inflight, batch, spin)
     tickets = [srv.submit(_request(it)) for it in items]    # a burst: requests queue and batch
     outs = []
     for t, it in zip(tickets, items):
