@@ -3,12 +3,15 @@
     python -m paper_2509_12494_amd.build [-v]
 
 Each source is compiled to an object under _build/ (in parallel), then linked
-with hipcc into paper_2509_12494_amd/libmwntt.so.  Always recompiles.
+with hipcc into paper_2509_12494_amd/libmwntt.so.  The binding's direct-call
+shim (csrc/mw_pycall.c, argument marshalling only) is compiled with the host C
+compiler into paper_2509_12494_amd/_mwcall<suffix>.so.  Always recompiles.
 """
 import concurrent.futures
 import os
 import subprocess
 import sys
+import sysconfig
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -49,6 +52,23 @@ def _compile(src, verbose):
     return obj
 
 
+PYCALL = os.path.join(HERE, "_mwcall" + sysconfig.get_config_var("EXT_SUFFIX"))
+
+
+def build_pycall(verbose: bool = False) -> str:
+    """The binding's direct-call shim (a CPython extension, no device code)."""
+    tmp = PYCALL + ".tmp"
+    cmd = ["gcc", "-O2", "-shared", "-fPIC", "-Wall", "-I" + sysconfig.get_paths()["include"],
+           os.path.join(CSRC, "mw_pycall.c"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("mw_pycall.c failed:\n" + r.stderr)
+    os.replace(tmp, PYCALL)
+    return PYCALL
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
@@ -61,6 +81,7 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
     os.replace(tmp, LIB)
+    build_pycall(verbose)
     return LIB
 
 

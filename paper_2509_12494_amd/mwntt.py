@@ -29,6 +29,17 @@ NTT_JOB_POLYMUL = 2
 
 _lib = None
 
+try:
+    # direct-call shim for the hot entry points (csrc/mw_pycall.c, built with
+    # the library): the same calls into libmwntt as through ctypes, with less
+    # per-call marshalling; without it the ctypes path below is used
+    from . import _mwcall
+except ImportError:
+    _mwcall = None
+
+_HOT = ("ntt_forward", "ntt_inverse", "vec_addmod", "vec_submod", "vec_mulmod", "vec_axpymod")
+_BLAS_OP = {"vec_addmod": 0, "vec_submod": 1, "vec_mulmod": 2}
+
 
 class NttJob(ctypes.Structure):
     _fields_ = [("plan", ctypes.c_void_p), ("op", ctypes.c_uint32), ("in_", ctypes.c_void_p),
@@ -114,6 +125,8 @@ def lib() -> ctypes.CDLL:
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    if _mwcall is not None:
+        _mwcall.bind(*(ctypes.cast(getattr(L, n), ctypes.c_void_p).value for n in _HOT))
     _lib = L
     return L
 
@@ -145,6 +158,14 @@ def _words(x: int, limbs: int, size: int = 4):
     for i in range(limbs):
         arr[i] = (x >> (64 * i)) & (2**64 - 1)
     return arr
+
+
+@functools.lru_cache(maxsize=1024)
+def _words_ref(x: int, limbs: int):
+    """(array, address) of _words(x, limbs), for the direct-call shim; the
+    caller holds the tuple while the call runs."""
+    arr = _words(x, limbs)
+    return arr, ctypes.addressof(arr)
 
 
 def _from_words(arr, limbs: int) -> int:
@@ -183,7 +204,12 @@ def _count(t, limbs: int, n: Optional[int]) -> int:
 # ---------------------------------------------------------------------------
 def _blas(name, c, a, b, q, limbs, n, stream):
     n = _count(c, limbs, n)
-    st = getattr(lib(), name)(_ptr(c), _ptr(a), _ptr(b), n, _words(q, limbs), limbs, _stream(stream))
+    L = lib()
+    if _mwcall is not None:
+        qref = _words_ref(q, limbs)
+        st = _mwcall.blas(_BLAS_OP[name], _ptr(c), _ptr(a), _ptr(b), n, qref[1], limbs, _stream(stream))
+    else:
+        st = getattr(L, name)(_ptr(c), _ptr(a), _ptr(b), n, _words(q, limbs), limbs, _stream(stream))
     _check(st, name)
 
 
@@ -201,7 +227,12 @@ def vec_mulmod(c, a, b, q: int, limbs: int, n: Optional[int] = None, stream=None
 
 def vec_axpymod(y, alpha: int, x, q: int, limbs: int, n: Optional[int] = None, stream=None) -> None:
     n = _count(y, limbs, n)
-    st = lib().vec_axpymod(_ptr(y), _words(alpha, limbs), _ptr(x), n, _words(q, limbs), limbs, _stream(stream))
+    L = lib()
+    if _mwcall is not None:
+        aref, qref = _words_ref(alpha, limbs), _words_ref(q, limbs)
+        st = _mwcall.axpy(_ptr(y), aref[1], _ptr(x), n, qref[1], limbs, _stream(stream))
+    else:
+        st = L.vec_axpymod(_ptr(y), _words(alpha, limbs), _ptr(x), n, _words(q, limbs), limbs, _stream(stream))
     _check(st, "vec_axpymod")
 
 
@@ -257,7 +288,13 @@ class NttPlan:
 
     def forward(self, out, inp, batch: Optional[int] = None, stream=None) -> None:
         b = self._batch(inp, batch)
-        _check(lib().ntt_forward(self._h, _ptr(out), _ptr(inp), b, _stream(stream)), "ntt_forward")
+        L = lib()
+        if _mwcall is not None:
+            hv = self._h.value if self._h is not None else None
+            st = _mwcall.ntt(0, hv, _ptr(out), _ptr(inp), b, _stream(stream))
+        else:
+            st = L.ntt_forward(self._h, _ptr(out), _ptr(inp), b, _stream(stream))
+        _check(st, "ntt_forward")
 
     def forward_pass(self, pass_: int, out, inp, batch: int, stream=None) -> None:
         """Pass 1 (column tiles, inp -> plan scratch) or 2 (row tiles, scratch -> out)."""
@@ -267,7 +304,13 @@ class NttPlan:
 
     def inverse(self, out, inp, batch: Optional[int] = None, stream=None) -> None:
         b = self._batch(inp, batch)
-        _check(lib().ntt_inverse(self._h, _ptr(out), _ptr(inp), b, _stream(stream)), "ntt_inverse")
+        L = lib()
+        if _mwcall is not None:
+            hv = self._h.value if self._h is not None else None
+            st = _mwcall.ntt(1, hv, _ptr(out), _ptr(inp), b, _stream(stream))
+        else:
+            st = L.ntt_inverse(self._h, _ptr(out), _ptr(inp), b, _stream(stream))
+        _check(st, "ntt_inverse")
 
     def destroy(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -128,3 +128,29 @@ def test_tile_argument_errors_without_device():
     L = mwntt.lib()
     assert L.ntt_plan_set_tiles(None, 1, 3, 8) == -1
     assert L.ntt_plan_set_split(None, 4) == -1
+
+
+def test_direct_call_shim_matches_ctypes():
+    """The binding's direct-call shim (built with the library) reaches the
+    same entry points as ctypes: identical statuses on host-checked paths."""
+    import ctypes
+    assert mwntt._mwcall is not None, "the shim is built by build() beside the library"
+    L = mwntt.lib()
+    sh = mwntt._mwcall
+    q124 = W.find_prime(124, 1001)
+    q60 = W.find_prime(60, 1)
+    for q, limbs, n, ptr in ((q124, 2, 0, 0), (q124, 2, 5, 0), (q60, 2, 5, 8), (q124, 3, 5, 8), (q60, 1, 0, 8)):
+        qw = mwntt._words(q, min(limbs, 4))
+        qa = ctypes.addressof(qw)
+        for op, name in enumerate(("vec_addmod", "vec_submod", "vec_mulmod")):
+            want = getattr(L, name)(ptr, ptr, ptr, n, qw, limbs, None)
+            assert sh.blas(op, ptr, ptr, ptr, n, qa, limbs, None) == want, (name, q.bit_length(), limbs, n)
+        aw = mwntt._words(q - 1, min(limbs, 4))
+        want = L.vec_axpymod(ptr, aw, ptr, n, qw, limbs, None)
+        assert sh.axpy(ptr, ctypes.addressof(aw), ptr, n, qa, limbs, None) == want
+    for d, name in ((0, "ntt_forward"), (1, "ntt_inverse")):
+        assert sh.ntt(d, None, 8, 8, 1, None) == getattr(L, name)(None, 8, 8, 1, None) == -1
+    with pytest.raises(ValueError):
+        sh.ntt(2, None, 0, 0, 1, None)
+    with pytest.raises(TypeError):
+        sh.blas(0, 0, 0)
