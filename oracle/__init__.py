@@ -19,5 +19,11 @@ Everything is written from the paper's definitions in plain Python integers
 Readings of the paper that the oracle takes where the text is silent
 (negacyclic twist, choice of root, inverse scaling, output order) are listed in
 each module's docstring.
+
+Pins: ``tests/oracle_pins.py`` (run by ``tests/test_oracle.py``) checks every
+function here against the paper's worked example, closed forms, brute force on
+small moduli and independent evaluations, at small and at 60-, 124- and 252-bit
+primes; ``tests/test_oracle_mutations.py`` plants plausible mistakes in this
+package and checks that each one fails a pin.
 """
 from . import modarith, roots, ntt, polymul  # noqa: F401
