@@ -154,3 +154,21 @@ def test_direct_call_shim_matches_ctypes():
         sh.ntt(2, None, 0, 0, 1, None)
     with pytest.raises(TypeError):
         sh.blas(0, 0, 0)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built HIP library every entry point raises: there is no CPU
+    fallback in the product path."""
+    saved_path, saved_lib = mwntt.LIB_PATH, mwntt._lib
+    try:
+        mwntt.LIB_PATH = str(tmp_path / "libmwntt.so")
+        mwntt._lib = None
+        with pytest.raises(RuntimeError, match="missing"):
+            mwntt.lib()
+        with pytest.raises(RuntimeError, match="missing"):
+            mwntt.vec_addmod(0, 0, 0, 17, 1, n=0, stream=0)
+        with pytest.raises(RuntimeError, match="missing"):
+            mwntt.ntt_plan(4, 97, 1)
+    finally:
+        mwntt.LIB_PATH, mwntt._lib = saved_path, saved_lib
+        mwntt.lib()   # rebinds the direct-call shim to the real library
