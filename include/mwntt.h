@@ -30,8 +30,9 @@
  * for vec_mulmod, 2 <= bitlen(q) <= 60 otherwise.  limbs == 2:
  * 97 <= bitlen(q) <= 124 for vec_mulmod, 61 <= bitlen(q) <= 124 otherwise.
  * limbs == 4: 225 <= bitlen(q) <= 252 for vec_mulmod, 125 <= bitlen(q) <= 252
- * otherwise.  Other limb counts are MW_EINVAL.  q must be odd.  Primality is the caller's responsibility (an NTT plan checks
- * that its root has order exactly 2N).
+ * otherwise.  Other limb counts are MW_EINVAL.  q must be odd.  Primality is
+ * the caller's responsibility (an NTT plan checks that its root has order
+ * exactly 2N).
  *
  * Streams and errors.  `stream` is a hipStream_t (NULL = the null stream).
  * Argument errors return a negative status synchronously and enqueue nothing.
