@@ -15,7 +15,7 @@ op's stream); algorithmic Gmulmod/s; the batched (96 transforms per call)
 rate; ``legs``: the executor on the same batch, a batch sweep, a
 host-inclusive (pinned copies in and out) figure, the mixed 96-polynomial
 batch and its inverse, 256 fused products at 2^14, RNS products over eight
-primes, the 252-bit transform and BLAS, BLAS at streaming sizes (2^24) against
+primes, the 60-bit and 252-bit transforms and BLAS, BLAS at streaming sizes (2^24) against
 the HBM peak, and the serving replay; the roofline
 of the dominant kernel (with HBM traffic and VALU instructions from the
 committed rocprofv3 summary); and the CPU oracle's rate on a bounded sample.
@@ -438,6 +438,28 @@ def main():
     for pl in rplans:
         pl.destroy()
     del rjobs
+
+    # the same paper-scale transform with a 60-bit prime (one word), for
+    # comparison with the 124-bit figures: plain latency, 96 per call, mulmod
+    progress("60-bit leg")
+    q1 = W.find_prime(60, 2001)
+    p60 = mwntt.ntt_plan(16, q1, 1)
+    x60 = mwntt.to_device(W.uniform_residues(W.rng(6050), q1, n * 96, 1))
+    y60, z60 = torch.empty_like(x60), torch.empty_like(x60)
+    p60.forward(y60, x60, batch=96, stream=sp)
+    p60.inverse(z60, y60, batch=96, stream=sp)
+    torch.cuda.synchronize()
+    assert torch.equal(z60, x60), "60-bit round trip failed"
+    b60_us = time_calls(lambda: p60.forward(y60, x60, batch=96, stream=sp), stream, reps=10)
+    x1, y1, z1, x2 = x60[:n], y60[:n], z60[:n], x60[n:2 * n]
+    legs["plain_60bit_2e16"] = {
+        "q_bits": 60, "N": n,
+        "ntt_forward_us": round(time_calls(lambda: p60.forward(y1, x1, batch=1, stream=sp), stream, reps=50), 2),
+        "ntt_inverse_us": round(time_calls(lambda: p60.inverse(z1, y1, batch=1, stream=sp), stream, reps=50), 2),
+        "batch": 96, "batched_us_per_call": round(b60_us, 2), "batched_ntt_s": round(96 / (b60_us * 1e-6), 1),
+        "vec_mulmod_us": round(time_calls(lambda: mwntt.vec_mulmod(z1, x1, x2, q1, 1, stream=sp), stream, reps=50), 2)}
+    p60.destroy()
+    del x60, y60, z60, x1, y1, z1, x2
 
     # four-word moduli (252-bit q = 1 mod 2^18): N = 2^16, plain latency,
     # batch-64 throughput and the BLAS ops, inputs resident in HBM
