@@ -94,6 +94,22 @@ struct ExecParams {
   const ModConst<8>* mods8;
   const ModConst<4>* mods4;
   const ModConst<2>* mods2;
+  // A run of one job: its descriptor and constants travel in the kernel
+  // arguments instead of device memory (no upload before the first launch),
+  // and tile = workgroup index (column phases in XCD order).
+  u32 one;                 // 1: the fields below are used, jobs / items / mods* are not
+  u32 one_phase;
+  u32 one_xcd;             // the phase's tiles are column tiles
+  u32 one_pad;
+  JobDesc one_job;
+  ModConst<8> one_m8;      // the one filled for the job's width
+  ModConst<4> one_m4;
+  ModConst<2> one_m2;
 };
+static_assert(sizeof(ExecParams) <= 4096, "kernel arguments are limited to 4 KiB");
+
+// Launches the phases of a run of exactly one job with its descriptor in the
+// kernel arguments (no device copy of the descriptors is needed).
+hipError_t exec_launch_one(const ExecPlan& plan, hipStream_t s);
 
 }  // namespace mw

@@ -139,16 +139,12 @@ __device__ __forceinline__ void run_fused_row(const NttParams<W>& pf, const NttP
 }
 
 template <int W, int LOGP, bool FIXED>
-__device__ __forceinline__ void run_item(const ExecParams& ep, const JobDesc& J, u32 job, u32 phase, u32 tile,
+__device__ __forceinline__ void run_item(const JobDesc& J, const ModConst<W>& mc, u32 phase, u32 tile,
                                          unsigned char* smem) {
-  const ModConst<W>* mc;
-  if constexpr (W == 8) mc = ep.mods8 + job;
-  else if constexpr (W == 4) mc = ep.mods4 + job;
-  else mc = ep.mods2 + job;
   NttParams<W> p;
-  p.M = mc->M;
-  p.ninv = mc->ninv;
-  p.ninv_w1 = mc->last;
+  p.M = mc.M;
+  p.ninv = mc.ninv;
+  p.ninv_w1 = mc.last;
   p.log_n = J.log_n;
   p.log_n1 = J.log_n1;
   p.batch = 1;
@@ -208,8 +204,21 @@ __global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(4)
   const uint2 it = ep.items[blockIdx.x];
   const u32 job = it.x & 0xffffu, limbs = it.x >> 16, phase = it.y >> 16, tile = it.y & 0xffffu;
   const JobDesc J = ep.jobs[job];
-  if (limbs == 2) run_item<4, kLogP4, false>(ep, J, job, phase, tile, mw_exec_smem);
-  else run_item<2, kLogP2, false>(ep, J, job, phase, tile, mw_exec_smem);
+  if (limbs == 2) run_item<4, kLogP4, false>(J, ep.mods4[job], phase, tile, mw_exec_smem);
+  else run_item<2, kLogP2, false>(J, ep.mods2[job], phase, tile, mw_exec_smem);
+}
+
+template <int W>
+__device__ __forceinline__ const ModConst<W>* mods_of(const ExecParams& ep) {
+  if constexpr (W == 8) return ep.mods8;
+  else if constexpr (W == 4) return ep.mods4;
+  else return ep.mods2;
+}
+template <int W>
+__device__ __forceinline__ const ModConst<W>& one_mods_of(const ExecParams& ep) {
+  if constexpr (W == 8) return ep.one_m8;
+  else if constexpr (W == 4) return ep.one_m4;
+  else return ep.one_m2;
 }
 
 // Tiles of one width (W 32-bit words per residue), with the specialised tile
@@ -221,7 +230,21 @@ __global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(4)
   const u32 job = it.x & 0xffffu, phase = it.y >> 16, tile = it.y & 0xffffu;
   const JobDesc J = ep.jobs[job];
   constexpr int LOGP = W == 8 ? kLogP8 : (W == 4 ? kLogP4 : kLogP2);
-  run_item<W, LOGP, true>(ep, J, job, phase, tile, mw_exec_smem);
+  run_item<W, LOGP, true>(J, mods_of<W>(ep)[job], phase, tile, mw_exec_smem);
+}
+
+// The tiles of a run of one job, whose descriptor and constants are kernel
+// arguments (a kernel of its own: reading them through a pointer that may
+// also point to device memory would move the constants into vector
+// registers).  tile = workgroup index, column phases in XCD order.  Its runs
+// are small, so it may take the registers of 3 waves per SIMD (at 4 the
+// constants held in scalar registers push the two-word tiles into a spill).
+template <int W>
+__global__ __launch_bounds__(kExecThreads) __attribute__((amdgpu_waves_per_eu(3))) void exec_kernel_one(ExecParams ep) {
+  extern __shared__ __align__(16) unsigned char mw_exec_smem[];
+  constexpr int LOGP = W == 8 ? kLogP8 : (W == 4 ? kLogP4 : kLogP2);
+  const u32 tile = ep.one_xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+  run_item<W, LOGP, true>(ep.one_job, one_mods_of<W>(ep), ep.one_phase, tile, mw_exec_smem);
 }
 
 // host twin of xcd_tile: the tile that position b of a run of n tiles takes
@@ -343,19 +366,47 @@ hipError_t exec_prepare(const ExecPlan& plan) {
       hipError_t r = raise_lds(exec_kernel, 65537);
       if (r == hipSuccess) r = raise_lds(exec_kernel_w<2>, 65537);
       if (r == hipSuccess) r = raise_lds(exec_kernel_w<4>, 65537);
+      if (r == hipSuccess) r = raise_lds(exec_kernel_one<2>, 65537);
+      if (r == hipSuccess) r = raise_lds(exec_kernel_one<4>, 65537);
       return r;
     }();
     if (e != hipSuccess) return e;
   }
   if (lds8 > 65536) {
-    static const hipError_t e8 = raise_lds(exec_kernel_w<8>, 65537);
+    static const hipError_t e8 = [] {
+      const hipError_t r = raise_lds(exec_kernel_w<8>, 65537);
+      return r == hipSuccess ? raise_lds(exec_kernel_one<8>, 65537) : r;
+    }();
     if (e8 != hipSuccess) return e8;
   }
   return hipSuccess;
 }
 
+hipError_t exec_launch_one(const ExecPlan& plan, hipStream_t s) {
+  if (plan.jobs.size() != 1) return hipErrorInvalidValue;
+  const JobDesc& d = plan.jobs[0];
+  ExecParams ep = {};
+  ep.one = 1;
+  ep.one_job = d;
+  ep.one_m8 = plan.m8[0];
+  ep.one_m4 = plan.m4[0];
+  ep.one_m2 = plan.m2[0];
+  for (u32 k = 0; k < d.nphases; ++k) {
+    ep.one_phase = k;
+    // the same column-phase rule as the item lists' XCD order
+    ep.one_xcd = d.op == JOB_FWD ? k == 0 : (d.op == JOB_INV ? k == 1 : k != 1);
+    const dim3 grid(d.tiles[k]), block(kExecThreads);
+    if (d.limbs == 4) hipLaunchKernelGGL(exec_kernel_one<8>, grid, block, plan.phase_lds8[k], s, ep);
+    else if (d.limbs == 2) hipLaunchKernelGGL(exec_kernel_one<4>, grid, block, plan.phase_lds[k], s, ep);
+    else hipLaunchKernelGGL(exec_kernel_one<2>, grid, block, plan.phase_lds[k], s, ep);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t exec_launch(const ExecDevice& d, const ExecPlan& plan, hipStream_t s) {
-  ExecParams ep;
+  ExecParams ep = {};
   ep.jobs = d.jobs;
   ep.mods8 = d.m8;
   ep.mods4 = d.m4;
@@ -464,8 +515,11 @@ extern "C" int ntt_batch_create(ntt_batch_t* out, const ntt_job* jobs, uint32_t 
 
 extern "C" int ntt_batch_run(ntt_batch_t batch, void* stream) {
   if (!batch) return MW_EINVAL;
+  // (a batch's descriptors are already in device memory, so even a batch of
+  // one job runs from them: measured faster than the kernel-argument form)
+  const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const ExecDevice d{batch->d_jobs, batch->d_items, batch->d_items8, batch->d_m8, batch->d_m4, batch->d_m2};
-  return exec_launch(d, batch->plan, reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+  return exec_launch(d, batch->plan, s) == hipSuccess
              ? MW_OK
              : MW_EDEVICE;
 }

@@ -9,7 +9,8 @@
 // requests become complete and their scratch returns to the pool), then, while
 // a slot is free, admits requests from the head of the queue as long as their
 // memory fits and the batch has room, uploads the batch's descriptors with
-// one asynchronous copy and launches it (transform / product requests through
+// one asynchronous copy (a batch of one transform or product passes its
+// descriptor in the kernel arguments instead, with no copy) and launches it (transform / product requests through
 // the batched executor, BLAS requests as their own kernels) on the slot's
 // stream.  Requests arriving meanwhile wait in the queue and go into the next
 // batch on the next free slot, so batches overlap on the device.
@@ -177,6 +178,26 @@ namespace {
 
 void* pool_ptr(mw_server_s* S, size_t off) { return S->pool_base ? (char*)S->pool_base + off : nullptr; }
 
+// Several transforms / products: descriptors packed into the slot's pinned
+// block, sent with one copy, then the executor's launches.
+bool launch_packed(Slot& slot, const ExecPlan& plan) {
+  const size_t nj = plan.jobs.size(), ni = plan.items.size(), ni8 = plan.items8.size();
+  const DescLayout L = desc_layout(nj, ni, ni8);
+  std::memcpy(slot.h_desc + L.jobs, plan.jobs.data(), sizeof(JobDesc) * nj);
+  std::memcpy(slot.h_desc + L.m8, plan.m8.data(), sizeof(ModConst<8>) * nj);
+  std::memcpy(slot.h_desc + L.m4, plan.m4.data(), sizeof(ModConst<4>) * nj);
+  std::memcpy(slot.h_desc + L.m2, plan.m2.data(), sizeof(ModConst<2>) * nj);
+  std::memcpy(slot.h_desc + L.items, plan.items.data(), sizeof(uint2) * ni);
+  std::memcpy(slot.h_desc + L.items8, plan.items8.data(), sizeof(uint2) * ni8);
+  if (hipMemcpyAsync(slot.d_desc, slot.h_desc, L.total, hipMemcpyHostToDevice, slot.stream) != hipSuccess)
+    return false;
+  char* b = slot.d_desc;
+  const ExecDevice d{(const JobDesc*)(b + L.jobs), (const uint2*)(b + L.items), (const uint2*)(b + L.items8),
+                     (const ModConst<8>*)(b + L.m8), (const ModConst<4>*)(b + L.m4),
+                     (const ModConst<2>*)(b + L.m2)};
+  return exec_launch(d, plan, slot.stream) == hipSuccess;
+}
+
 // Launch one batch on a slot (called with the lock held).
 bool launch_batch(mw_server_s* S, Slot& slot, const std::vector<uint64_t>& batch) {
   slot.tickets = batch;
@@ -208,22 +229,13 @@ bool launch_batch(mw_server_s* S, Slot& slot, const std::vector<uint64_t>& batch
         plan.items8.size() > (size_t)S->cfg.max_batch * kMaxTilesPerJob)
       return false;
     for (size_t i = 0; i < jobs.size(); ++i) plan.jobs[i].scratch = (u64)pool_ptr(S, S->reqs[job_tickets[i]].scratch_off);
-    const size_t nj = plan.jobs.size(), ni = plan.items.size(), ni8 = plan.items8.size();
-    const DescLayout L = desc_layout(nj, ni, ni8);
-    std::memcpy(slot.h_desc + L.jobs, plan.jobs.data(), sizeof(JobDesc) * nj);
-    std::memcpy(slot.h_desc + L.m8, plan.m8.data(), sizeof(ModConst<8>) * nj);
-    std::memcpy(slot.h_desc + L.m4, plan.m4.data(), sizeof(ModConst<4>) * nj);
-    std::memcpy(slot.h_desc + L.m2, plan.m2.data(), sizeof(ModConst<2>) * nj);
-    std::memcpy(slot.h_desc + L.items, plan.items.data(), sizeof(uint2) * ni);
-    std::memcpy(slot.h_desc + L.items8, plan.items8.data(), sizeof(uint2) * ni8);
-    if (hipMemcpyAsync(slot.d_desc, slot.h_desc, L.total, hipMemcpyHostToDevice, slot.stream) != hipSuccess)
-      return false;
     if (exec_prepare(plan) != hipSuccess) return false;
-    char* b = slot.d_desc;
-    const ExecDevice d{(const JobDesc*)(b + L.jobs), (const uint2*)(b + L.items), (const uint2*)(b + L.items8),
-                       (const ModConst<8>*)(b + L.m8), (const ModConst<4>*)(b + L.m4),
-                       (const ModConst<2>*)(b + L.m2)};
-    if (exec_launch(d, plan, slot.stream) != hipSuccess) return false;
+    if (jobs.size() == 1) {
+      // one transform or product: its descriptor goes in the kernel arguments
+      if (exec_launch_one(plan, slot.stream) != hipSuccess) return false;
+    } else if (!launch_packed(slot, plan)) {
+      return false;
+    }
   }
   for (uint64_t t : batch) {
     Req& R = S->reqs[t];

@@ -471,3 +471,46 @@ def test_batch_argument_errors():
     assert e.value.status == -2
     mwntt.NttBatch([(p200, mwntt.NTT_JOB_FORWARD, z, None, z)]).destroy()   # transforms are fine
     p200.destroy()
+
+
+@pytest.mark.parametrize("bits", [60, 124, 252])
+def test_single_job_batches_match_plain(bits):
+    """Batches of a single job (the smallest runs of the executor): every op
+    (and order flags) at N = 2^6, 2^10, 2^14, 2^17, against the plain entry
+    points, repeated runs, sampled outputs to the oracle."""
+    require_gpu()
+    import torch
+    limbs = W.limbs_for_bits(bits)
+    g = W.rng(9500 + bits)
+    for log2n in (6, 10, 14, 17):
+        for op in (mwntt.NTT_JOB_FORWARD, mwntt.NTT_JOB_INVERSE, mwntt.NTT_JOB_POLYMUL):
+            flags = 0
+            if op == mwntt.NTT_JOB_FORWARD and log2n == 14:
+                flags = mwntt.NTT_BITREV_OUT
+            if op == mwntt.NTT_JOB_INVERSE and log2n == 10:
+                flags = mwntt.NTT_BITREV_IN
+            q = prime(bits, 70 + log2n % 3)
+            plan = mwntt.ntt_plan(log2n, q, limbs, flags=flags)
+            n = plan.n
+            A, B = W.uniform_residues(g, q, n, limbs), W.uniform_residues(g, q, n, limbs)
+            a, b = dev(A), dev(B)
+            out = torch.empty_like(a)
+            batch = mwntt.NttBatch([(plan, op, a, b if op == mwntt.NTT_JOB_POLYMUL else None, out)])
+            announce("single job", bits, log2n, op, flags, batch.info())
+            want = _plain(plan, op, a, b)
+            for rep in range(2):
+                out.zero_()
+                batch.run()
+                batch.check()
+                assert torch.equal(out, want), f"N 2^{log2n} op {op} flags {flags} run {rep}"
+            if log2n <= 10:
+                ks = [0, n - 1, (log2n * 37) % n]
+                got = host_ints(out, limbs)
+                a_i, b_i = W.to_ints(A), W.to_ints(B)
+                if op == mwntt.NTT_JOB_POLYMUL:
+                    assert [got[k] for k in ks] == oracle.polymul.negacyclic_at(a_i, b_i, q, ks)
+                elif op == mwntt.NTT_JOB_FORWARD:
+                    pos = [bitrev(k, log2n) if flags & mwntt.NTT_BITREV_OUT else k for k in ks]
+                    assert [got[p_] for p_ in pos] == oracle.ntt.forward_at(a_i, q, ks)
+            batch.destroy()
+            plan.destroy()

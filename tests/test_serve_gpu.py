@@ -150,3 +150,32 @@ def test_replay_poisson_gpu():
     srv.destroy()
     for p in plans.values():
         p.destroy()
+
+
+def test_one_request_at_a_time_matches_alone():
+    """Each request submitted only after the previous one completed, so every
+    batch holds one job (its descriptor then travels in the kernel
+    arguments): transforms and products of every width at N = 2^6 .. 2^17,
+    each result against the same operation alone and sampled against the
+    oracle."""
+    require_gpu()
+    import torch
+    items, plans = _workload(42, seed=31, log2_range=(6, 17), wide=True)
+    srv = mwntt.MwServer(1 << 30, max_inflight=2, max_batch=8)
+    announce("serve one at a time", len(items))
+    for i, it in enumerate(items):
+        t = srv.submit(_request(it))
+        ptr, lat = srv.result(t, wait=True)
+        out = mwntt.copy_to_tensor(ptr, it["a"])
+        torch.cuda.synchronize()
+        srv.release(t)
+        assert torch.equal(out, _alone(it)), f"request {i} op {it['op']} n {it['n']} limbs {it['limbs']}"
+        if i % 6 == 0:
+            ks = [0, it["n"] - 1, (i * 41) % it["n"]]
+            got = host_ints(out, it["limbs"])
+            assert [got[k] for k in ks] == _oracle_sample(it, ks), f"request {i}"
+    st = srv.stats()
+    assert st["completed"] == len(items) and st["max_batch_seen"] == 1
+    srv.destroy()
+    for p in plans.values():
+        p.destroy()
