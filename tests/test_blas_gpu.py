@@ -154,3 +154,32 @@ def test_sub_range_of_buffer():
     got = host_ints(c, 2)
     assert got[:2049] == oracle.modarith.vec_addmod(W.to_ints(A)[:2049], W.to_ints(A)[:2049], q)
     assert got[2049:] == [0] * (3000 - 2049)
+
+
+@pytest.mark.parametrize("bits,seed", [(61, 17), (125, 18), (200, 19)])
+@pytest.mark.parametrize("n", [1, 1000, 4099])
+def test_add_sub_axpy_low_widths(n, bits, seed):
+    """Add, sub and axpy at widths below Barrett's range for their limb class
+    (61 bits in two words, 125 and 200 in four): whole outputs against the
+    oracle; vec_mulmod rejects these widths (checked on the host)."""
+    require_gpu()
+    import torch
+    q = prime(bits, seed)
+    limbs = W.limbs_for_bits(bits)
+    g = W.rng(n * 11 + bits)
+    A = W.uniform_residues(g, q, n, limbs)
+    B = W.uniform_residues(g, q, n, limbs)
+    alpha = W.uniform_scalar(g, q, limbs)
+    announce("low width", n, bits)
+    a, b = dev(A), dev(B)
+    for op in ("vec_addmod", "vec_submod"):
+        c = torch.empty_like(a)
+        getattr(mwntt, op)(c, a, b, q, limbs)
+        torch.cuda.synchronize()
+        assert host_ints(c, limbs) == _oracle(op, W.to_ints(A), W.to_ints(B), q), op
+    y = b.clone()
+    mwntt.vec_axpymod(y, alpha, a, q, limbs)
+    torch.cuda.synchronize()
+    assert host_ints(y, limbs) == [(alpha * x + z) % q for x, z in zip(W.to_ints(A), W.to_ints(B))]
+    with pytest.raises(mwntt.MwError):
+        mwntt.vec_mulmod(torch.empty_like(a), a, b, q, limbs)

@@ -357,3 +357,28 @@ def test_ctypes_and_direct_call_paths_agree(bits, seed):
     ks = [0, n - 1, 1234 % n]
     assert [got[k] for k in ks] == oracle.ntt.forward_at(W.to_ints(A[:n]), q, ks)
     plan.destroy()
+
+
+@pytest.mark.parametrize("bits,seed", [(61, 24), (97, 25), (125, 26), (200, 27)])
+@pytest.mark.parametrize("log2n", [5, 9, 13, 16])
+def test_edge_widths(bits, seed, log2n):
+    """Moduli at the low end of each limb class (61 bits in two words, 125 in
+    four) and between the classes' ends: the lazy ranges and quotient
+    estimates hold for every q of a class, not only the widest.  Whole
+    outputs against the definition up to 2^9, sampled beyond; round trip."""
+    require_gpu()
+    q, limbs, A = _case(bits, seed, log2n, 2)
+    n = 1 << log2n
+    announce("edge width", bits, log2n)
+    plan = mwntt.ntt_plan(log2n, q, limbs)
+    y = _run(plan, A, "fwd", batch=2)
+    got = host_ints(y, limbs)
+    a0 = W.to_ints(A[:n])
+    if log2n <= 9:
+        assert got[:n] == oracle.ntt.ntt_negacyclic(a0, q)
+    else:
+        ks = [0, 1, n // 2, n - 1, (seed * 977) % n]
+        assert [got[k] for k in ks] == oracle.ntt.forward_at(a0, q, ks)
+    back = _run(plan, W.from_ints(got, limbs), "inv", batch=2)
+    assert host_ints(back, limbs) == W.to_ints(A)
+    plan.destroy()
