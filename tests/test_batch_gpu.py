@@ -514,3 +514,45 @@ def test_single_job_batches_match_plain(bits):
                     assert [got[p_] for p_ in pos] == oracle.ntt.forward_at(a_i, q, ks)
             batch.destroy()
             plan.destroy()
+
+
+def test_edge_width_jobs_match_plain():
+    """Executor jobs at the low ends of the width classes: products (point-wise
+    Barrett in the fused rows) at 97 and 225 bits, the smallest widths Barrett
+    takes in two and four words, and transforms at 61 and 125 bits, in one
+    mixed batch and in single-width batches, against the plain entry points."""
+    require_gpu()
+    import torch
+    specs = [(10, 97, mwntt.NTT_JOB_POLYMUL), (14, 97, mwntt.NTT_JOB_POLYMUL), (16, 97, mwntt.NTT_JOB_FORWARD),
+             (10, 225, mwntt.NTT_JOB_POLYMUL), (13, 225, mwntt.NTT_JOB_POLYMUL), (12, 125, mwntt.NTT_JOB_INVERSE),
+             (15, 61, mwntt.NTT_JOB_FORWARD), (11, 61, mwntt.NTT_JOB_INVERSE), (14, 125, mwntt.NTT_JOB_FORWARD)]
+    g = W.rng(9700)
+    jobs, refs = [], []
+    for k, (log2n, bits, op) in enumerate(specs):
+        q = prime(bits, 80 + k % 2)
+        limbs = W.limbs_for_bits(bits)
+        plan = mwntt.ntt_plan(log2n, q, limbs)
+        A, B = W.uniform_residues(g, q, plan.n, limbs), W.uniform_residues(g, q, plan.n, limbs)
+        a, b = dev(A), dev(B)
+        out = torch.empty_like(a)
+        jobs.append((plan, op, a, b if op == mwntt.NTT_JOB_POLYMUL else None, out))
+        refs.append((plan, op, a, b, out, A, B))
+    groups = [list(range(len(jobs)))] + [[i for i, sp in enumerate(specs) if W.limbs_for_bits(sp[1]) == l]
+                                         for l in (2, 4)]
+    for gi, idx in enumerate(groups):
+        batch = mwntt.NttBatch([jobs[i] for i in idx])
+        announce("edge width jobs", gi, batch.info())
+        for i in idx:
+            refs[i][4].zero_()
+        batch.run()
+        batch.check()
+        for i in idx:
+            plan, op, a, b, out, A, B = refs[i]
+            assert torch.equal(out, _plain(plan, op, a, b)), f"group {gi} job {i} ({specs[i]})"
+            if op == mwntt.NTT_JOB_POLYMUL and plan.n <= 1 << 10:
+                ks = [0, plan.n - 1, 321]
+                got = host_ints(out, plan.limbs)
+                assert [got[k] for k in ks] == oracle.polymul.negacyclic_at(W.to_ints(A), W.to_ints(B), plan.q, ks)
+        batch.destroy()
+    for plan, *_ in refs:
+        plan.destroy()
