@@ -9,7 +9,7 @@ Everything is written from the paper's definitions in plain Python integers
 
 * ``modarith`` -- modular add / sub / mul and axpy (Background, modular
   arithmetic; polynomial operations as BLAS).
-* ``roots``    -- the canonical primitive 2N-th root of unity and inverses.
+* ``roots``    -- the canonical primitive 2N-th root of unity.
 * ``ntt``      -- the n-point transform of Eq. (ntt) by its definition, the
   negacyclic forward / inverse transforms built on it, and per-index
   evaluations for large N.

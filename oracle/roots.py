@@ -18,7 +18,6 @@ Construction (all by definition):
 Parity pins: tests/test_oracle.py (brute-force order search over all of Z_q
 for small primes; psi^N = -1 and psi^2N = 1 at the workload widths).
 """
-from typing import Tuple
 
 
 def check_ntt_modulus(q: int, n: int) -> None:
@@ -48,12 +47,3 @@ def canonical_psi(q: int, n: int) -> int:
             best = cur
     return best
 
-
-def inverse(x: int, q: int) -> int:
-    return pow(x, -1, q)
-
-
-def ntt_constants(q: int, n: int) -> Tuple[int, int, int]:
-    """(psi, psi^-1, N^-1) for the canonical root."""
-    psi = canonical_psi(q, n)
-    return psi, inverse(psi, q), inverse(n, q)
