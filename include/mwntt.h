@@ -24,15 +24,16 @@
  *
  * Values.  Every input residue must be canonical, 0 <= x < q (the paper's
  * assumption for Eq. saddmod / ssubmod); results for non-canonical inputs are
- * unspecified.  Every output is canonical.
+ * unspecified, and in validate mode (mw_set_validate) they are reported as
+ * MW_ENONCANON.  Every output is canonical.
  *
- * Moduli.  `q` points to `limbs` host words.  limbs == 1: 33 <= bitlen(q) <= 60
- * for vec_mulmod, 2 <= bitlen(q) <= 60 otherwise.  limbs == 2:
- * 97 <= bitlen(q) <= 124 for vec_mulmod, 61 <= bitlen(q) <= 124 otherwise.
- * limbs == 4: 225 <= bitlen(q) <= 252 for vec_mulmod, 125 <= bitlen(q) <= 252
- * otherwise.  Other limb counts are MW_EINVAL.  q must be odd.  Primality is
- * the caller's responsibility (an NTT plan checks that its root has order
- * exactly 2N).
+ * Moduli.  `q` points to `limbs` host words.  limbs == 1: 2 <= bitlen(q) <= 60
+ * (q >= 3); limbs == 2: 61 <= bitlen(q) <= 124; limbs == 4:
+ * 125 <= bitlen(q) <= 252.  Every operation takes every odd q of its class
+ * (Barrett's reduction, Eq. barrett, holds for general moduli; the library
+ * runs it on q scaled by a power of two to the top of the class).  Other limb
+ * counts are MW_EINVAL.  Primality is the caller's responsibility (an NTT plan
+ * checks that its root has order exactly 2N).
  *
  * Streams and errors.  `stream` is a hipStream_t (NULL = the null stream).
  * Argument errors return a negative status synchronously and enqueue nothing.
@@ -60,11 +61,37 @@ enum mw_status {
   MW_ENOMEM = -4,    /* device or host allocation failed */
   MW_EDEVICE = -5,   /* HIP runtime error (launch failure, no device) */
   MW_EROOT = -6,     /* supplied root is not a primitive 2N-th root */
-  MW_EBUSY = -7      /* serving: the request has not completed yet */
+  MW_EBUSY = -7,     /* serving: the request has not completed yet */
+  MW_ENONCANON = -8  /* validate mode: an input residue was >= q */
 };
 
 /* Returns a static string describing a status code. */
 const char* mw_status_str(int status);
+
+/* ------------------------------------------------------------------------ */
+/* Validate mode (input canonicality, the paper's precondition 0 <= x < q    */
+/* of Eq. saddmod / ssubmod).  While it is on, every entry point that reads  */
+/* caller residues (the BLAS calls, ntt_forward / ntt_inverse /             */
+/* ntt_forward_pass, ntt_batch_run, and the serving runtime's requests)     */
+/* first enqueues a check kernel over those inputs on the same stream; a     */
+/* residue >= q sets a library-wide error word held in pinned host memory.  */
+/* The violation is reported, and the word cleared, by mw_check (which      */
+/* synchronizes the stream first) or by the first entry point called after  */
+/* the check kernel has completed: that call returns MW_ENONCANON and       */
+/* enqueues nothing.  The work whose inputs failed still runs (its output   */
+/* is unspecified).  Off by default; the environment variable               */
+/* MWNTT_VALIDATE=1 turns it on when the library loads.  Costs one extra    */
+/* read of every input.                                                      */
+/* ------------------------------------------------------------------------ */
+/* on != 0 enables validation, 0 disables it (a pending error is kept).
+ * MW_ENOMEM if the pinned error word cannot be allocated. */
+int mw_set_validate(int on);
+/* 1 if validation is on, else 0. */
+int mw_get_validate(void);
+/* Synchronizes `stream`, then returns MW_ENONCANON (and clears the word) if
+ * a check kernel found a non-canonical input since the last report, MW_EDEVICE
+ * if the synchronization failed, else MW_OK. */
+int mw_check(void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Element-wise modular BLAS (Background, polynomial operations as BLAS).    */
@@ -172,7 +199,7 @@ enum ntt_job_op { NTT_JOB_FORWARD = 0, NTT_JOB_INVERSE = 1, NTT_JOB_POLYMUL = 2 
  * applies to forward outputs, NTT_BITREV_IN to inverse inputs; products take
  * and return natural order).  in / in2 / out are device buffers of N
  * residues; in2 is used by NTT_JOB_POLYMUL only (b; in is a).  out may alias
- * in or in2.  Products need the Barrett width rule of vec_mulmod. */
+ * in or in2. */
 typedef struct {
   ntt_plan_t plan;
   uint32_t op;
@@ -294,7 +321,9 @@ int mw_server_destroy(mw_server_t server);
 int mw_canonical_root(const uint64_t* q, uint32_t limbs, uint32_t log2n, uint64_t* psi_out);
 /* Shoup companion floor(w * 2^(64*limbs) / q) of a constant w < q. */
 int mw_shoup_companion(const uint64_t* w, const uint64_t* q, uint32_t limbs, uint64_t* out);
-/* Barrett constant floor(2^(2b) / q), b = bitlen(q) (b+1 bits, limbs words). */
+/* Barrett constant of the normalised modulus, floor(2^(2T) / q') with
+ * q' = q * 2^(T - bitlen(q)) and T = 60, 124, 252 for limbs 1, 2, 4 (T + 1
+ * bits, limbs words). */
 int mw_barrett_mu(const uint64_t* q, uint32_t limbs, uint64_t* out);
 /* Asynchronous copy of `bytes` between any two HIP-visible buffers on
  * `stream` (used to read server-owned outputs). */

@@ -23,11 +23,17 @@
 //     under-estimates the exact Shoup quotient by at most 4 (W=4) or 1 (W=2,
 //     W=8); the result x*w - Q*q is then in [0, 6q) for any x < 2^(32W).
 //   * Barrett reduction (Background, modular arithmetic, Eq. barrett) for a
-//     product of two variables, with k = 2*bitlen(q): mu = floor(2^(2b)/q),
-//     q1 = floor(x / 2^(b-1)), q3 = floor(q1*mu / 2^(b+1)), r = x - q3*q.
-//     q3 is at most 2 below floor(x/q) (plus 1 for the dropped low columns of
-//     q1*mu with W=4), so r < 4q and two conditional subtractions make it
-//     canonical.
+//     product of two variables.  The reduction holds for any modulus; to keep
+//     its shifts at fixed word offsets it runs on the normalised modulus
+//     q' = q * 2^s whose bit length is the top of the width class,
+//     T = 32W - 4 (60, 124 or 252 bits; s = T - bitlen(q)).  With k = 2T:
+//     mu = floor(2^(2T)/q'), q1 = floor(x / 2^(T-1)), q3 = floor(q1*mu /
+//     2^(T+1)), r = x - q3*q'.  q3 is at most 2 below floor(x/q') (plus 1 for
+//     the dropped low columns of q1*mu with W=4 and W=8), so r < 4q' and two
+//     conditional subtractions make it canonical.  Multiplying a*2^s by b
+//     modulo q' gives 2^s * (a*b mod q), and a right shift by s returns the
+//     residue mod q.  A modulus at the top of its class has s = 0 and skips
+//     both shifts (a uniform branch).
 //
 // Everything here is device code; host-side constants (w', mu) are produced by
 // the plan code with exact long division.
@@ -52,11 +58,18 @@ struct Modulus {
   u32 q2[W];   // 2q
   u32 q4[W];   // 4q
   u32 q8[W];   // 8q
-  u32 mu[W];   // Barrett mu = floor(2^(2b)/q) (b+1 bits)
   u32 negq[W]; // 2^(32W) - q
+  u32 qn[W];   // Barrett's normalised modulus q' = q * 2^shift, bitlen(q') = 32W - 4
+  u32 qn2[W];  // 2q'
+  u32 mu[W];   // Barrett mu = floor(2^(2(32W-4)) / q') (32W-3 bits)
   u32 bits;    // b = bitlen(q)
-  u32 pad_[3];
+  u32 shift;   // (32W - 4) - b
+  u32 pad_[2];
 };
+
+// Bit length of a normalised Barrett modulus of W words.
+template <int W>
+constexpr int barrett_bits() { return 32 * W - 4; }
 
 // ---------------------------------------------------------------------------
 // word-level primitives
@@ -475,19 +488,69 @@ __device__ __forceinline__ Res<W> shoup_mul(const Res<W>& x, const u32 (&w)[W], 
 // funnel shift: bits [s, s+32) of the 64-bit value hi:lo, 0 <= s < 32
 __device__ __forceinline__ u32 funnel(u32 hi, u32 lo, u32 s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
 
-// Barrett: canonical a*b mod q for a, b in [0, q).  W=4 requires
-// 97 <= bitlen(q) <= 124, W=2 requires 33 <= bitlen(q) <= 60.
-__device__ __forceinline__ Res<4> barrett_mul(const Res<4>& a, const Res<4>& b, const Modulus<4>& M) {
+// Word moves of the uniform shifts: by K, 2K, 4K, ... words where the
+// corresponding bit of ws is set, as selects (every index a compile-time
+// constant, so the residue stays in registers).
+template <int W, int K>
+__device__ __forceinline__ void words_up(Res<W>& t, u32 ws) {
+  if constexpr (K < W) {
+    const bool on = (ws & (u32)K) != 0;
+#pragma unroll
+    for (int i = W - 1; i >= 0; --i) t.v[i] = on ? (i >= K ? t.v[i - K] : 0u) : t.v[i];
+    words_up<W, 2 * K>(t, ws);
+  }
+}
+
+template <int W, int K>
+__device__ __forceinline__ void words_down(Res<W>& t, u32 ws) {
+  if constexpr (K < W) {
+    const bool on = (ws & (u32)K) != 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) t.v[i] = on ? (i + K < W ? t.v[i + K] : 0u) : t.v[i];
+    words_down<W, 2 * K>(t, ws);
+  }
+}
+
+// a * 2^s for a uniform 0 < s < 32W whose result fits in W words: a word
+// shift by s / 32 in log2(W) uniform steps, then a bit shift by s % 32.
+template <int W>
+__device__ __forceinline__ Res<W> shl_uniform(const Res<W>& a, u32 s) {
+  Res<W> t = a;
+  words_up<W, 1>(t, s >> 5);
+  const u32 bs = s & 31;
+  Res<W> r;
+#pragma unroll
+  for (int i = W - 1; i > 0; --i) r.v[i] = bs ? funnel(t.v[i], t.v[i - 1], 32u - bs) : t.v[i];
+  r.v[0] = t.v[0] << bs;
+  return r;
+}
+
+// a / 2^s for a uniform 0 < s < 32W (exact here: a is a multiple of 2^s).
+template <int W>
+__device__ __forceinline__ Res<W> shr_uniform(const Res<W>& a, u32 s) {
+  Res<W> t = a;
+  words_down<W, 1>(t, s >> 5);
+  const u32 bs = s & 31;
+  Res<W> r;
+#pragma unroll
+  for (int i = 0; i < W - 1; ++i) r.v[i] = funnel(t.v[i + 1], t.v[i], bs);
+  r.v[W - 1] = t.v[W - 1] >> bs;
+  return r;
+}
+
+// Barrett core on the normalised modulus (T = 124 bits): canonical x mod q'
+// for x = a*b < 2^248.  The shifts by T - 1 = 123 and T + 1 = 125 bits start
+// in word 3 at bit offsets 27 and 29.
+__device__ __forceinline__ Res<4> barrett_core(const Res<4>& a, const Res<4>& b, const Modulus<4>& M) {
   u32 x[8];
   mul_full(a, b, x);
-  // q1 = x >> (b-1), b-1 in [96, 123]: word offset 3
-  const u32 s1 = (M.bits - 1) & 31;
+  constexpr u32 s1 = (barrett_bits<4>() - 1) & 31;
   Res<4> q1;
   q1.v[0] = funnel(x[4], x[3], s1);
   q1.v[1] = funnel(x[5], x[4], s1);
   q1.v[2] = funnel(x[6], x[5], s1);
   q1.v[3] = funnel(x[7], x[6], s1);
-  // q2 = q1 * mu, columns >= 2 (dropped part < 2^98 <= 2^(b+1))
+  // q2 = q1 * mu, columns >= 2 (dropped part < 2^98 < 2^(T+1))
   u32 q2[8];
   {
     const u32* m = M.mu;
@@ -526,28 +589,27 @@ __device__ __forceinline__ Res<4> barrett_mul(const Res<4>& a, const Res<4>& b, 
     q2[6] = lo32(acc);
     q2[7] = hi32(acc);
   }
-  // q3 = q2 >> (b+1), b+1 in [98, 125]: word offset 3
-  const u32 s3 = (M.bits + 1) & 31;
+  constexpr u32 s3 = (barrett_bits<4>() + 1) & 31;
   Res<4> q3;
   q3.v[0] = funnel(q2[4], q2[3], s3);
   q3.v[1] = funnel(q2[5], q2[4], s3);
   q3.v[2] = funnel(q2[6], q2[5], s3);
   q3.v[3] = funnel(q2[7], q2[6], s3);
-  // r = x - q3*q  (mod 2^128; the true value is in [0, 4q))
+  // r = x - q3*q'  (mod 2^128; the true value is in [0, 4q'))
   Res<4> xl;
   xl.v[0] = x[0]; xl.v[1] = x[1]; xl.v[2] = x[2]; xl.v[3] = x[3];
-  Res<4> qq = mul_lo(q3, M.q);
+  Res<4> qq = mul_lo(q3, M.qn);
   u32 bo;
   Res<4> r = sub(xl, qq, bo);
-  r = csub(r, M.q2);
-  return csub(r, M.q);
+  r = csub(r, M.qn2);
+  return csub(r, M.qn);
 }
 
-__device__ __forceinline__ Res<2> barrett_mul(const Res<2>& a, const Res<2>& b, const Modulus<2>& M) {
+// T = 60 bits: the shifts by 59 and 61 bits start in word 1.
+__device__ __forceinline__ Res<2> barrett_core(const Res<2>& a, const Res<2>& b, const Modulus<2>& M) {
   u32 x[4];
   mul_full(a, b, x);
-  // q1 = x >> (b-1), b-1 in [32, 59]: word offset 1
-  const u32 s1 = (M.bits - 1) & 31;
+  constexpr u32 s1 = (barrett_bits<2>() - 1) & 31;
   Res<2> q1;
   q1.v[0] = funnel(x[2], x[1], s1);
   q1.v[1] = funnel(x[3], x[2], s1);
@@ -556,44 +618,59 @@ __device__ __forceinline__ Res<2> barrett_mul(const Res<2>& a, const Res<2>& b, 
   mu.v[1] = M.mu[1];
   u32 q2[4];
   mul_full(q1, mu, q2);
-  // q3 = q2 >> (b+1), b+1 in [34, 61]: word offset 1
-  const u32 s3 = (M.bits + 1) & 31;
+  constexpr u32 s3 = (barrett_bits<2>() + 1) & 31;
   Res<2> q3;
   q3.v[0] = funnel(q2[2], q2[1], s3);
   q3.v[1] = funnel(q2[3], q2[2], s3);
   Res<2> xl;
   xl.v[0] = x[0]; xl.v[1] = x[1];
-  Res<2> qq = mul_lo(q3, M.q);
+  Res<2> qq = mul_lo(q3, M.qn);
   u32 bo;
   Res<2> r = sub(xl, qq, bo);
-  r = csub(r, M.q2);
-  return csub(r, M.q);
+  r = csub(r, M.qn2);
+  return csub(r, M.qn);
 }
 
-// Barrett for W = 8 (225 <= bitlen(q) <= 252): the shifts by b - 1 and
-// b + 1 start in word 7; q1*mu drops columns 0..4 (less than 5 * 2^192 *
-// (1 + 2^-32) < 2^(b+1)), so q3 is at most 3 below floor(x/q) and r < 4q.
-__device__ __forceinline__ Res<8> barrett_mul(const Res<8>& a, const Res<8>& b, const Modulus<8>& M) {
+// T = 252 bits: the shifts by 251 and 253 bits start in word 7; q1*mu drops
+// columns 0..4 (less than 5 * 2^192 * (1 + 2^-32) < 2^(T+1)), so q3 is at
+// most 3 below floor(x/q') and r < 4q'.
+__device__ __forceinline__ Res<8> barrett_core(const Res<8>& a, const Res<8>& b, const Modulus<8>& M) {
   u32 x[16];
   mul_cols<8, 0>(a.v, b.v, x);
-  const u32 s1 = (M.bits - 1) & 31;
+  constexpr u32 s1 = (barrett_bits<8>() - 1) & 31;
   Res<8> q1;
 #pragma unroll
   for (int k = 0; k < 8; ++k) q1.v[k] = funnel(x[8 + k], x[7 + k], s1);
   u32 q2[11];   // words 5..15 of the truncated q1*mu
   mul_cols<8, 5>(q1.v, M.mu, q2);
-  const u32 s3 = (M.bits + 1) & 31;
+  constexpr u32 s3 = (barrett_bits<8>() + 1) & 31;
   Res<8> q3;
 #pragma unroll
   for (int k = 0; k < 8; ++k) q3.v[k] = funnel(q2[3 + k], q2[2 + k], s3);   // words 8+k : 7+k
   Res<8> xl;
 #pragma unroll
   for (int k = 0; k < 8; ++k) xl.v[k] = x[k];
-  Res<8> qq = mul_lo(q3, M.q);
+  Res<8> qq = mul_lo(q3, M.qn);
   u32 bo;
   Res<8> r = sub(xl, qq, bo);
-  r = csub(r, M.q2);
-  return csub(r, M.q);
+  r = csub(r, M.qn2);
+  return csub(r, M.qn);
+}
+
+// Barrett: canonical a*b mod q for a, b in [0, q), any odd q of the width
+// class.  a*2^s < q' and b < q <= q', so x = a*2^s*b < 2^(2T).  NORM (known
+// at compile time) selects the scaled form (M.shift > 0) or the plain one
+// (M.shift == 0); barrett_mul decides at run time with a uniform branch.
+template <int W, bool NORM>
+__device__ __forceinline__ Res<W> barrett_mul_t(const Res<W>& a, const Res<W>& b, const Modulus<W>& M) {
+  if constexpr (NORM) return shr_uniform(barrett_core(shl_uniform(a, M.shift), b, M), M.shift);
+  else return barrett_core(a, b, M);
+}
+
+template <int W>
+__device__ __forceinline__ Res<W> barrett_mul(const Res<W>& a, const Res<W>& b, const Modulus<W>& M) {
+  if (M.shift == 0) return barrett_mul_t<W, false>(a, b, M);
+  return barrett_mul_t<W, true>(a, b, M);
 }
 
 // ---------------------------------------------------------------------------

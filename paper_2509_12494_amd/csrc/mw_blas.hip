@@ -18,6 +18,7 @@
 
 #include "mw_arith.h"
 #include "mw_common.h"
+#include "mw_validate.h"
 
 namespace mw {
 
@@ -29,7 +30,9 @@ struct Scalar {
   u32 ws[W];
 };
 
-template <int W, int OP>
+// NORM: products reduce on the scaled modulus (a modulus below the top of its
+// width class; a kernel of its own, so the full-width one keeps its code).
+template <int W, int OP, bool NORM>
 __device__ __forceinline__ Res<W> blas_elem(const Res<W>& a, const Res<W>& b, const Modulus<W>& M,
                                            const Scalar<W>& s) {
   if constexpr (OP == OP_ADD) {
@@ -37,7 +40,7 @@ __device__ __forceinline__ Res<W> blas_elem(const Res<W>& a, const Res<W>& b, co
   } else if constexpr (OP == OP_SUB) {
     return submod(a, b, M);
   } else if constexpr (OP == OP_MUL) {
-    return barrett_mul(a, b, M);
+    return barrett_mul_t<W, NORM>(a, b, M);
   } else {
     // a = x, b = y: alpha*x in [0, 6q), + y in [0, 7q) -> canonical
     Res<W> t = shoup_mul(a, s.w, s.ws, M);
@@ -80,7 +83,7 @@ struct Stream<4> {
   }
 };
 
-template <int W, int OP, int VEC>
+template <int W, int OP, int VEC, bool NORM>
 __global__ __launch_bounds__(256) void blas_kernel(Res<W>* c, const Res<W>* a,
                                                    const Res<W>* b, u64 n, Modulus<W> M,
                                                    Scalar<W> s) {
@@ -95,14 +98,14 @@ __global__ __launch_bounds__(256) void blas_kernel(Res<W>* c, const Res<W>* a,
       y[v] = Stream<W>::load(b + base + (u64)v * blockDim.x);
     }
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) Stream<W>::store(c + base + (u64)v * blockDim.x, blas_elem<W, OP>(x[v], y[v], M, s));
+    for (int v = 0; v < VEC; ++v) Stream<W>::store(c + base + (u64)v * blockDim.x, blas_elem<W, OP, NORM>(x[v], y[v], M, s));
   }
   // ragged tail: residues [nfull*chunk, n), handled by the one block whose
   // turn comes next in the grid-stride order
   if (blockIdx.x == (unsigned)(nfull % gridDim.x)) {
     for (u64 i = nfull * chunk + threadIdx.x; i < n; i += blockDim.x) {
       Res<W> x = ResIO<W>::load(a + i), y = ResIO<W>::load(b + i);
-      ResIO<W>::store(c + i, blas_elem<W, OP>(x, y, M, s));
+      ResIO<W>::store(c + i, blas_elem<W, OP, NORM>(x, y, M, s));
     }
   }
 }
@@ -117,9 +120,14 @@ static int launch_blas(void* d_c, const void* d_a, const void* d_b, size_t n, co
   // at most 8 blocks per CU in flight; beyond that the grid-stride loop iterates
   u64 grid = chunks < 2048 ? chunks : 2048;
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL((blas_kernel<W, OP, VEC>), dim3((unsigned)grid), dim3(THREADS), 0, stream,
-                     reinterpret_cast<Res<W>*>(d_c), reinterpret_cast<const Res<W>*>(d_a),
-                     reinterpret_cast<const Res<W>*>(d_b), (u64)n, M, s);
+  if (OP == OP_MUL && M.shift != 0)
+    hipLaunchKernelGGL((blas_kernel<W, OP, VEC, true>), dim3((unsigned)grid), dim3(THREADS), 0, stream,
+                       reinterpret_cast<Res<W>*>(d_c), reinterpret_cast<const Res<W>*>(d_a),
+                       reinterpret_cast<const Res<W>*>(d_b), (u64)n, M, s);
+  else
+    hipLaunchKernelGGL((blas_kernel<W, OP, VEC, false>), dim3((unsigned)grid), dim3(THREADS), 0, stream,
+                       reinterpret_cast<Res<W>*>(d_c), reinterpret_cast<const Res<W>*>(d_a),
+                       reinterpret_cast<const Res<W>*>(d_b), (u64)n, M, s);
   return hipGetLastError() == hipSuccess ? MW_OK : MW_EDEVICE;
 }
 
@@ -176,17 +184,24 @@ static int memo_scalar(const uint64_t* alpha, const uint64_t* q, uint32_t limbs,
   return MW_OK;
 }
 
+// report: a pending validate-mode violation is returned by this call (the
+// public entry points); the serving runtime leaves it for mw_check.
 template <int OP>
 static int blas_dispatch(void* d_c, const void* d_a, const void* d_b, size_t n, const uint64_t* q,
-                         uint32_t limbs, const uint64_t* alpha, void* stream) {
+                         uint32_t limbs, const uint64_t* alpha, void* stream, bool report = true) {
   if (!q || (limbs != 1 && limbs != 2 && limbs != 4)) return MW_EINVAL;
   if (n == 0) return MW_OK;
   if (!d_c || !d_a || !d_b) return MW_EINVAL;
   if (n > ((size_t)1 << 40)) return MW_EINVAL;
-  int st = check_modulus(q, limbs, OP == OP_MUL);
+  int st = check_modulus(q, limbs);
   if (st != MW_OK) return st;
   if (OP == OP_AXPY && !alpha) return MW_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (validate_on()) {
+    if (report && (st = validate_take()) != MW_OK) return st;
+    if ((st = validate_input(d_a, n, q, limbs, s)) != MW_OK) return st;
+    if ((st = validate_input(d_b, n, q, limbs, s)) != MW_OK) return st;
+  }
   if (limbs == 4) {
     Scalar<8> sc = {};
     if (OP == OP_AXPY && memo_scalar<8>(alpha, q, limbs, sc) != MW_OK) return MW_EINVAL;
@@ -207,10 +222,10 @@ static int blas_dispatch(void* d_c, const void* d_a, const void* d_b, size_t n, 
 int blas_launch(int op, void* d_c, const void* d_a, const void* d_b, size_t n, const uint64_t* q, uint32_t limbs,
                 const uint64_t* alpha, void* stream) {
   switch (op) {
-    case OP_ADD: return blas_dispatch<OP_ADD>(d_c, d_a, d_b, n, q, limbs, nullptr, stream);
-    case OP_SUB: return blas_dispatch<OP_SUB>(d_c, d_a, d_b, n, q, limbs, nullptr, stream);
-    case OP_MUL: return blas_dispatch<OP_MUL>(d_c, d_a, d_b, n, q, limbs, nullptr, stream);
-    case OP_AXPY: return blas_dispatch<OP_AXPY>(d_c, d_a, d_b, n, q, limbs, alpha, stream);
+    case OP_ADD: return blas_dispatch<OP_ADD>(d_c, d_a, d_b, n, q, limbs, nullptr, stream, false);
+    case OP_SUB: return blas_dispatch<OP_SUB>(d_c, d_a, d_b, n, q, limbs, nullptr, stream, false);
+    case OP_MUL: return blas_dispatch<OP_MUL>(d_c, d_a, d_b, n, q, limbs, nullptr, stream, false);
+    case OP_AXPY: return blas_dispatch<OP_AXPY>(d_c, d_a, d_b, n, q, limbs, alpha, stream, false);
     default: return MW_EINVAL;
   }
 }

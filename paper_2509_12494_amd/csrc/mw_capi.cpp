@@ -15,6 +15,7 @@ extern "C" const char* mw_status_str(int status) {
     case MW_EDEVICE: return "HIP device error";
     case MW_EROOT: return "not a primitive 2N-th root of unity";
     case MW_EBUSY: return "request not complete";
+    case MW_ENONCANON: return "input residue not canonical (validate mode)";
     default: return "unknown status";
   }
 }
@@ -69,16 +70,20 @@ extern "C" int mw_shoup_companion(const uint64_t* w, const uint64_t* q, uint32_t
   return MW_OK;
 }
 
+// Barrett constant of the normalised modulus: mu = floor(2^(2T) / q'),
+// q' = q * 2^(T - bitlen(q)), T = 60, 124 or 252 for 1, 2 or 4 limbs.
 extern "C" int mw_barrett_mu(const uint64_t* q, uint32_t limbs, uint64_t* out) {
   if (!q || !out || (limbs != 1 && limbs != 2 && limbs != 4)) return MW_EINVAL;
   if (limbs == 4) {
     const mwhost::U256 Q = mwhost::u256_from_words(q, 4);
     if (!wide_ok(Q)) return MW_EMODULUS;
-    mwhost::u256_to_words(mwhost::pow2_div(2 * mwhost::bitlen(Q), Q), out, 4);
+    const mwhost::U256 Qn = mwhost::shl_any(Q, 252 - mwhost::bitlen(Q));
+    mwhost::u256_to_words(mwhost::pow2_div(2 * 252, Qn), out, 4);
     return MW_OK;
   }
   mwhost::u128 Q = mwhost::from_words(q, limbs);
   if (!width_ok(Q, limbs)) return MW_EMODULUS;
-  mwhost::to_words(mwhost::pow2_div(2 * mwhost::bitlen(Q), Q), out, limbs);
+  const int T = limbs == 1 ? 60 : 124;
+  mwhost::to_words(mwhost::pow2_div(2 * T, Q << (T - mwhost::bitlen(Q))), out, limbs);
   return MW_OK;
 }

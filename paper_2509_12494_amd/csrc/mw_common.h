@@ -10,18 +10,15 @@
 
 namespace mw {
 
-// Width rules (see mwntt.h): limbs == 1 -> q < 2^60, limbs == 2 ->
-// 2^60 <= q < 2^124, limbs == 4 -> 2^124 <= q < 2^252.  Barrett
-// multiplication additionally needs bitlen(q) >= 33 (limbs 1), >= 97
-// (limbs 2) or >= 225 (limbs 4): its shifts by b - 1 and b + 1 bits then
-// start in the top word of the lower half of a double-width value.
-inline int check_modulus(const uint64_t* q, uint32_t limbs, bool barrett) {
+// Width rules (see mwntt.h): limbs == 1 -> odd 3 <= q < 2^60, limbs == 2 ->
+// 2^60 <= q < 2^124, limbs == 4 -> 2^124 <= q < 2^252.  Every operation
+// (Barrett multiplication included) takes any odd modulus of its class.
+inline int check_modulus(const uint64_t* q, uint32_t limbs) {
   if (!q || (limbs != 1 && limbs != 2 && limbs != 4)) return MW_EINVAL;
   if (limbs == 4) {
     const mwhost::U256 Q = mwhost::u256_from_words(q, 4);
     const int b = mwhost::bitlen(Q);
     if (!(Q.w[0] & 1) || b > 252 || b < 125) return MW_EMODULUS;
-    if (barrett && b < 225) return MW_EMODULUS;
     return MW_OK;
   }
   mwhost::u128 Q = mwhost::from_words(q, limbs);
@@ -29,10 +26,8 @@ inline int check_modulus(const uint64_t* q, uint32_t limbs, bool barrett) {
   if (!(Q & 1) || Q < 3) return MW_EMODULUS;
   if (limbs == 1) {
     if (b > 60) return MW_EMODULUS;
-    if (barrett && b < 33) return MW_EMODULUS;
   } else {
     if (b > 124 || b < 61) return MW_EMODULUS;
-    if (barrett && b < 97) return MW_EMODULUS;
   }
   return MW_OK;
 }
@@ -50,10 +45,16 @@ inline void make_modulus(const uint64_t* q, uint32_t limbs, Modulus<W>& M) {
   put_words<W>(2 * Q, M.q2);
   put_words<W>(4 * Q, M.q4);
   put_words<W>(8 * Q, M.q8);
-  put_words<W>(mwhost::pow2_div(2 * b, Q), M.mu);
   put_words<W>((mwhost::u128)0 - Q, M.negq);  // 2^(32W) - q (W = 4: 2^128 - q)
+  // Barrett on q' = q * 2^s with bitlen(q') = 32W - 4
+  const int T = barrett_bits<W>();
+  const mwhost::u128 Qn = Q << (T - b);
+  put_words<W>(Qn, M.qn);
+  put_words<W>(2 * Qn, M.qn2);
+  put_words<W>(mwhost::pow2_div(2 * T, Qn), M.mu);
   M.bits = (u32)b;
-  M.pad_[0] = M.pad_[1] = M.pad_[2] = 0;
+  M.shift = (u32)(T - b);
+  M.pad_[0] = M.pad_[1] = 0;
 }
 
 template <int W>
@@ -69,10 +70,15 @@ inline void make_modulus(const uint64_t* q, Modulus<8>& M) {
   put_words<8>(mwhost::shl(Q, 1), M.q2);
   put_words<8>(mwhost::shl(Q, 2), M.q4);
   put_words<8>(mwhost::shl(Q, 3), M.q8);            // 8q < 2^255
-  put_words<8>(mwhost::pow2_div(2 * b, Q), M.mu);
   put_words<8>(mwhost::sub(mwhost::u256(0), Q), M.negq);  // 2^256 - q
+  const int T = barrett_bits<8>();
+  const mwhost::U256 Qn = mwhost::shl_any(Q, T - b);
+  put_words<8>(Qn, M.qn);
+  put_words<8>(mwhost::shl(Qn, 1), M.qn2);                 // 2q' < 2^253
+  put_words<8>(mwhost::pow2_div(2 * T, Qn), M.mu);
   M.bits = (u32)b;
-  M.pad_[0] = M.pad_[1] = M.pad_[2] = 0;
+  M.shift = (u32)(T - b);
+  M.pad_[0] = M.pad_[1] = 0;
 }
 
 inline int make_scalar(const uint64_t* w, const uint64_t* q, u32 (&wv)[8], u32 (&ws)[8]) {

@@ -112,4 +112,8 @@ static_assert(sizeof(ExecParams) <= 4096, "kernel arguments are limited to 4 KiB
 // kernel arguments (no device copy of the descriptors is needed).
 hipError_t exec_launch_one(const ExecPlan& plan, hipStream_t s);
 
+// Validate mode: enqueues the canonicality check of every job's inputs on s
+// (see mw_set_validate).  MW_OK or a negative status.
+int exec_validate(const ExecPlan& plan, hipStream_t s);
+
 }  // namespace mw

@@ -36,6 +36,7 @@
 #include "mw_common.h"
 #include "mw_exec.h"
 #include "mw_ntt_rt.h"
+#include "mw_validate.h"
 
 namespace mw {
 
@@ -103,11 +104,15 @@ __device__ __forceinline__ void fixed_fused_row(const NttParams<W>& pf, const Nt
   const u32 base = (1u << pf.log_n1) + row0 + line_id;
   line_stages<W, LOGL, LOGP, DIR_FWD>(la + line_id * S::NPAD, lane, base, pf.tw, pf, false, true);
   line_stages<W, LOGL, LOGP, DIR_FWD>(lb + line_id * S::NPAD, lane, base, pf.tw, pf, false, true);
+  const auto pointwise = [&](auto norm) {
 #pragma unroll
-  for (int k = 0; k < P; ++k) {
-    const u32 idx = slot(t + (u32)k * kExecThreads);
-    la[idx] = barrett_mul(la[idx], lb[idx], pf.M);
-  }
+    for (int k = 0; k < P; ++k) {
+      const u32 idx = slot(t + (u32)k * kExecThreads);
+      la[idx] = barrett_mul_t<W, decltype(norm)::value>(la[idx], lb[idx], pf.M);
+    }
+  };
+  if (pf.M.shift) pointwise(std::true_type{});
+  else pointwise(std::false_type{});
   __syncthreads();
   line_stages<W, LOGL, LOGP, DIR_INV>(la + line_id * S::NPAD, lane, base, pi.tw, pi, false, false);
   const auto all = [](u32) { return true; };
@@ -280,7 +285,7 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
     c2 = {};
     if (!plan_view(jb.plan, v, c8, c4, c2)) return MW_EINVAL;
     if (v.log2n < 6) return MW_ESIZE;   // two-pass tiles need N1, N2 >= 8
-    if (jb.op == NTT_JOB_POLYMUL && check_modulus(v.q, v.limbs, true) != MW_OK) return MW_EMODULUS;
+    if (jb.op == NTT_JOB_POLYMUL && check_modulus(v.q, v.limbs) != MW_OK) return MW_EMODULUS;
     JobDesc& d = out.jobs[i];
     d = {};
     d.in = (u64)jb.in;
@@ -438,6 +443,23 @@ hipError_t exec_launch(const ExecDevice& d, const ExecPlan& plan, hipStream_t s)
 
 using namespace mw;
 
+namespace mw {
+// Validate mode: enqueue the canonicality checks of every job's inputs.
+int exec_validate(const ExecPlan& plan, hipStream_t s) {
+  for (size_t i = 0; i < plan.jobs.size(); ++i) {
+    const JobDesc& d = plan.jobs[i];
+    const u32* qw = d.limbs == 4 ? plan.m8[i].M.q : (d.limbs == 2 ? plan.m4[i].M.q : plan.m2[i].M.q);
+    uint64_t q[4] = {0, 0, 0, 0};
+    for (u32 k = 0; k < 2 * d.limbs; ++k) q[k / 2] |= (uint64_t)qw[k] << (32 * (k % 2));
+    const uint64_t n = (uint64_t)1 << d.log_n;
+    int st = validate_input(reinterpret_cast<const void*>(d.in), n, q, d.limbs, s);
+    if (st == MW_OK && d.op == JOB_MUL) st = validate_input(reinterpret_cast<const void*>(d.in2), n, q, d.limbs, s);
+    if (st != MW_OK) return st;
+  }
+  return MW_OK;
+}
+}  // namespace mw
+
 struct ntt_batch_s {
   int device = 0;
   ExecPlan plan;
@@ -518,6 +540,11 @@ extern "C" int ntt_batch_run(ntt_batch_t batch, void* stream) {
   // (a batch's descriptors are already in device memory, so even a batch of
   // one job runs from them: measured faster than the kernel-argument form)
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (validate_on()) {
+    int st = validate_take();
+    if (st == MW_OK) st = exec_validate(batch->plan, s);
+    if (st != MW_OK) return st;
+  }
   const ExecDevice d{batch->d_jobs, batch->d_items, batch->d_items8, batch->d_m8, batch->d_m4, batch->d_m2};
   return exec_launch(d, batch->plan, s) == hipSuccess
              ? MW_OK

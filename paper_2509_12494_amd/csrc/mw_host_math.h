@@ -4,7 +4,8 @@
 // double-and-add loop (exact, no division instruction), and the precomputed
 // constants of the device reductions come from bitwise long division:
 //   shoup(w)   = floor(w * 2^(64L) / q)                     (Shoup companion)
-//   barrett_mu = floor(2^(2b) / q), b = bitlen(q)            (Eq. barrett)
+//   barrett_mu = floor(2^(2T) / q'), q' = q * 2^(T - bitlen(q))  (Eq. barrett
+//                on the modulus normalised to T = 60 or 124 bits)
 // The canonical root of unity is the smallest primitive 2N-th root modulo q
 // (the paper's Eq. (ntt) leaves the choice of root open).
 #pragma once
@@ -61,7 +62,7 @@ inline u128 shoup(u128 w, u128 q, int shift) {
   return quo;
 }
 
-// floor(2^e / q) for q odd >= 3, e <= 2*124; result below 2^126
+// floor(2^e / q) for q >= 1 below 2^124, e <= 2 * bitlen(q); result below 2^126
 inline u128 pow2_div(int e, u128 q) {
   u128 quo = 0, rem = 0;
   for (int i = e; i >= 0; --i) {

@@ -79,6 +79,15 @@ inline U256 shl(const U256& a, int s) {  // 0 <= s < 64
   return r;
 }
 
+inline U256 shl_any(U256 a, int s) {  // 0 <= s < 256, bits above 2^256 dropped
+  while (s >= 64) {
+    for (int i = 3; i > 0; --i) a.w[i] = a.w[i - 1];
+    a.w[0] = 0;
+    s -= 64;
+  }
+  return shl(a, s);
+}
+
 inline int bitlen(const U256& a) {
   for (int i = 3; i >= 0; --i) {
     if (a.w[i]) return 64 * i + 64 - __builtin_clzll(a.w[i]);
@@ -114,7 +123,7 @@ inline U256 shr_window(const uint64_t (&x)[8], int s) {
   return r;
 }
 
-// floor(2^e / q) for odd q >= 3, bitlen(q) <= 252, e <= 2 * bitlen(q); the
+// floor(2^e / q) for q >= 1, bitlen(q) <= 252, e <= 2 * bitlen(q); the
 // quotient has at most e - bitlen(q) + 1 <= 253 bits.
 inline U256 pow2_div(int e, const U256& q) {
   U256 quo = u256(0), rem = u256(0);

@@ -17,6 +17,7 @@
 #include "mw_exec.h"
 #include "mw_ntt_tile.h"
 #include "mw_tuned.h"
+#include "mw_validate.h"
 
 namespace mw {
 // Largest single-workgroup transform and points-per-lane exponent of a width
@@ -249,11 +250,22 @@ int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, 
   return e == hipSuccess ? MW_OK : MW_EDEVICE;
 }
 
+// Validate mode: report a pending violation, then check `batch` polynomials
+// at d_in (see mw_set_validate).
+int validate_polys(const ntt_plan_s* P, const void* d_in, uint32_t batch, hipStream_t s) {
+  if (!validate_on()) return MW_OK;
+  int st = validate_take();
+  if (st != MW_OK) return st;
+  return validate_input(d_in, (uint64_t)batch << P->log2n, P->q, P->limbs, s);
+}
+
 int transform(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, void* stream, int dir) {
   if (!plan) return MW_EINVAL;
   if (batch == 0) return MW_OK;
   if (!d_out || !d_in) return MW_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int vs = validate_polys(plan, d_in, batch, s);
+  if (vs != MW_OK) return vs;
   switch (plan->limbs) {
     case 4: return run_transform<8>(plan, d_out, d_in, batch, dir, s);
     case 2: return run_transform<4>(plan, d_out, d_in, batch, dir, s);
@@ -439,7 +451,7 @@ extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint
   *out = nullptr;
   if (flags & ~(NTT_BITREV_OUT | NTT_BITREV_IN)) return MW_EINVAL;
   if (log2n < 1 || log2n > 17) return MW_ESIZE;
-  int st = check_modulus(q, limbs, false);
+  int st = check_modulus(q, limbs);
   if (st != MW_OK) return st;
   ntt_plan_s* P = new (std::nothrow) ntt_plan_s();
   if (!P) return MW_ENOMEM;
@@ -513,6 +525,10 @@ extern "C" int ntt_forward_pass(ntt_plan_t plan, uint32_t pass, void* d_out, con
   if (batch == 0) return MW_OK;
   if ((pass == 1 && !d_in) || (pass == 2 && !d_out)) return MW_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (validate_on()) {
+    const int vs = pass == 1 ? validate_polys(plan, d_in, batch, s) : validate_take();
+    if (vs != MW_OK) return vs;
+  }
   switch (plan->limbs) {
     case 4: return run_pass<8>(plan, pass, d_out, d_in, batch, s);
     case 2: return run_pass<4>(plan, pass, d_out, d_in, batch, s);

@@ -264,11 +264,17 @@ __device__ __forceinline__ void rt_fused_row(const NttParams<W>& pf, const NttPa
   const u32 base = (1u << log_n1) + row0 + line_id;
   rt_line_stages<W, LOGP, DIR_FWD, false, true>(la + line_id * npad, active, logl, lane, base, pf.tw, pf);
   rt_line_stages<W, LOGP, DIR_FWD, false, true>(lb + line_id * npad, active, logl, lane, base, pf.tw, pf);
-  for (u32 e = t; e < nelem; e += nthreads) {
-    const u32 j = e >> logl, l = e & (L - 1);
-    const u32 idx = j * npad + rt_pad<LOGP>(l, logl);
-    la[idx] = barrett_mul(la[idx], lb[idx], pf.M);
-  }
+  // point-wise Barrett products; the scaled or plain form is chosen once for
+  // the loop (a uniform branch on the job's modulus)
+  const auto pointwise = [&](auto norm) {
+    for (u32 e = t; e < nelem; e += nthreads) {
+      const u32 j = e >> logl, l = e & (L - 1);
+      const u32 idx = j * npad + rt_pad<LOGP>(l, logl);
+      la[idx] = barrett_mul_t<W, decltype(norm)::value>(la[idx], lb[idx], pf.M);
+    }
+  };
+  if (pf.M.shift) pointwise(std::true_type{});
+  else pointwise(std::false_type{});
   __syncthreads();
   rt_line_stages<W, LOGP, DIR_INV, false, false>(la + line_id * npad, active, logl, lane, base, pi.tw, pi);
   copy_staged<W, P>(

@@ -32,6 +32,7 @@
 
 #include "mw_common.h"
 #include "mw_exec.h"
+#include "mw_validate.h"
 
 namespace mw {
 int blas_launch(int op, void* d_c, const void* d_a, const void* d_b, size_t n, const uint64_t* q, uint32_t limbs,
@@ -230,6 +231,7 @@ bool launch_batch(mw_server_s* S, Slot& slot, const std::vector<uint64_t>& batch
       return false;
     for (size_t i = 0; i < jobs.size(); ++i) plan.jobs[i].scratch = (u64)pool_ptr(S, S->reqs[job_tickets[i]].scratch_off);
     if (exec_prepare(plan) != hipSuccess) return false;
+    if (validate_on() && exec_validate(plan, slot.stream) != MW_OK) return false;
     if (jobs.size() == 1) {
       // one transform or product: its descriptor goes in the kernel arguments
       if (exec_launch_one(plan, slot.stream) != hipSuccess) return false;
@@ -319,7 +321,11 @@ void scheduler(mw_server_s* S) {
       S->stats.inflight_peak = std::max<uint64_t>(S->stats.inflight_peak, S->inflight);
       S->stats.pool_peak = std::max(S->stats.pool_peak, S->pool.used());
       if (!launch_batch(S, *slot, batch)) {
-        // the batch could not be launched: fail its requests, free the slot
+        // the batch could not be launched: part of it may already be queued on
+        // the slot's stream (kernels, the descriptor copy from the slot's
+        // pinned block), so wait for the stream before its scratch, outputs
+        // and pinned block are reused; then fail its requests, free the slot
+        if (!S->cfg.dry_run) (void)hipStreamSynchronize(slot->stream);
         for (uint64_t tk : batch) {
           Req& R = S->reqs[tk];
           R.state = RQ_FAILED;
@@ -365,7 +371,7 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
     if (v.log2n < 6) return MW_ESIZE;
     if (op == MW_REQ_POLYMUL) {
       if (!r.in2) return MW_EINVAL;
-      if (check_modulus(v.q, v.limbs, true) != MW_OK) return MW_EMODULUS;
+      if (check_modulus(v.q, v.limbs) != MW_OK) return MW_EMODULUS;
     }
     const size_t bytes = (size_t)8 * v.limbs << v.log2n;
     R.out_bytes = round_up(bytes);
@@ -374,7 +380,7 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
   } else {
     if (!r.in2 || r.n == 0) return MW_EINVAL;
     if (r.n > (uint64_t(1) << 40)) return MW_EINVAL;   // the BLAS length limit; keeps 8*limbs*n exact
-    int st = check_modulus(r.q, r.limbs, op == MW_REQ_VEC_MULMOD);
+    int st = check_modulus(r.q, r.limbs);
     if (st != MW_OK) return st;
     if (op == MW_REQ_VEC_AXPYMOD) {
       const mwhost::U256 Q = mwhost::u256_from_words(r.q, r.limbs), A = mwhost::u256_from_words(r.alpha, r.limbs);
@@ -474,12 +480,16 @@ extern "C" int mw_server_result(mw_server_t S, uint64_t ticket, int wait, void**
   auto it = S->reqs.find(ticket);
   if (it == S->reqs.end()) return MW_EINVAL;
   if (wait) {
+    // the entry can be erased meanwhile (mw_server_release on another thread,
+    // or replay's collector): look it up by find() so a wait never inserts one
     S->cv_done.wait(lk, [&] {
-      const ReqState s = S->reqs[ticket].state;
-      return s == RQ_DONE || s == RQ_FAILED;
+      const auto f = S->reqs.find(ticket);
+      return f == S->reqs.end() || f->second.state == RQ_DONE || f->second.state == RQ_FAILED;
     });
+    it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return MW_EINVAL;
   }
-  Req& R = S->reqs[ticket];
+  Req& R = it->second;
   if (R.state == RQ_QUEUED || R.state == RQ_RUNNING) return MW_EBUSY;
   if (R.state == RQ_FAILED) return MW_EDEVICE;
   if (d_out) *d_out = pool_ptr(S, R.out_off);

@@ -49,6 +49,7 @@ class NttJob(ctypes.Structure):
 MW_REQ_NTT_FORWARD, MW_REQ_NTT_INVERSE, MW_REQ_POLYMUL = 0, 1, 2
 MW_REQ_VEC_ADDMOD, MW_REQ_VEC_SUBMOD, MW_REQ_VEC_MULMOD, MW_REQ_VEC_AXPYMOD = 3, 4, 5, 6
 MW_EBUSY = -7
+MW_ENONCANON = -8
 
 
 class MwRequest(ctypes.Structure):
@@ -120,6 +121,9 @@ def lib() -> ctypes.CDLL:
         "mw_canonical_root": (ctypes.c_int, [u64p, u32, u32, u64p]),
         "mw_shoup_companion": (ctypes.c_int, [u64p, u64p, u32, u64p]),
         "mw_barrett_mu": (ctypes.c_int, [u64p, u32, u64p]),
+        "mw_set_validate": (ctypes.c_int, [ctypes.c_int]),
+        "mw_get_validate": (ctypes.c_int, []),
+        "mw_check": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -459,6 +463,22 @@ def copy_to_tensor(ptr: int, like, stream=None):
     nbytes = out.numel() * out.element_size()
     _check(lib().mw_copy(out.data_ptr(), ptr, nbytes, _stream(stream)), "mw_copy")
     return out
+
+
+# ---------------------------------------------------------------------------
+# validate mode (input canonicality checks)
+# ---------------------------------------------------------------------------
+def set_validate(on: bool) -> None:
+    _check(lib().mw_set_validate(1 if on else 0), "mw_set_validate")
+
+
+def get_validate() -> bool:
+    return bool(lib().mw_get_validate())
+
+
+def check(stream=None) -> None:
+    """Synchronizes the stream; raises MwError(MW_ENONCANON) if a checked input was not canonical."""
+    _check(lib().mw_check(_stream(stream)), "mw_check")
 
 
 # ---------------------------------------------------------------------------

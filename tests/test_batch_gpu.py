@@ -464,13 +464,7 @@ def test_batch_argument_errors():
     y = torch.zeros(256, 1, dtype=torch.int64, device="cuda")
     with pytest.raises(mwntt.MwError):
         mwntt.NttBatch([(p60, mwntt.NTT_JOB_POLYMUL, y, None, y)])   # product without b
-    p200 = mwntt.ntt_plan(8, prime(200, 41), 4)   # four-word product below Barrett's 225 bits
-    z = torch.zeros(256, 4, dtype=torch.int64, device="cuda")
-    with pytest.raises(mwntt.MwError) as e:
-        mwntt.NttBatch([(p200, mwntt.NTT_JOB_POLYMUL, z, z, z)])
-    assert e.value.status == -2
-    mwntt.NttBatch([(p200, mwntt.NTT_JOB_FORWARD, z, None, z)]).destroy()   # transforms are fine
-    p200.destroy()
+    p60.destroy()
 
 
 @pytest.mark.parametrize("bits", [60, 124, 252])
@@ -555,4 +549,53 @@ def test_edge_width_jobs_match_plain():
                 assert [got[k] for k in ks] == oracle.polymul.negacyclic_at(W.to_ints(A), W.to_ints(B), plan.q, ks)
         batch.destroy()
     for plan, *_ in refs:
+        plan.destroy()
+
+
+# Odd widths across the three classes for the fused products (point-wise
+# Barrett on the scaled modulus): 12289 (14 bits, q = 1 mod 2^12) and 65537
+# (17 bits, q = 1 mod 2^16) written out, the rest seeded primes.
+PRODUCT_WIDTHS = [14, 17, 33, 59, 61, 80, 96, 97, 123, 125, 160, 200, 224, 225, 251]
+
+
+def _product_modulus(bits):
+    return {14: 12289, 17: 65537}.get(bits) or prime(bits, 900 + bits)
+
+
+def test_products_every_width():
+    """Fused negacyclic products at every width-class position, one mixed
+    batch (N = 2^6 .. 2^8 whole outputs against the oracle's schoolbook
+    product), then each job again as a batch of its own (kernel-argument
+    path) against the same outputs."""
+    require_gpu()
+    import torch
+    jobs, checks, plans = [], [], []
+    for k, bits in enumerate(PRODUCT_WIDTHS):
+        q = _product_modulus(bits)
+        limbs = W.limbs_for_bits(bits)
+        log2n = 6 + k % 3
+        plan = mwntt.ntt_plan(log2n, q, limbs)
+        plans.append(plan)
+        g = W.rng(9900 + bits)
+        A, B = W.uniform_residues(g, q, plan.n, limbs), W.uniform_residues(g, q, plan.n, limbs)
+        a, b = dev(A), dev(B)
+        out = torch.empty_like(a)
+        jobs.append((plan, mwntt.NTT_JOB_POLYMUL, a, b, out))
+        checks.append((out, limbs, oracle.polymul.negacyclic(W.to_ints(A), W.to_ints(B), q), bits))
+    batch = mwntt.NttBatch(jobs)
+    announce("products every width", batch.info())
+    batch.run()
+    batch.check()
+    for out, limbs, want, bits in checks:
+        assert host_ints(out, limbs) == want, f"{bits}-bit product"
+    batch.destroy()
+    for job, (out, limbs, want, bits) in zip(jobs, checks):
+        announce("single product", bits)
+        out.zero_()
+        one = mwntt.NttBatch([job])
+        one.run()
+        one.check()
+        assert host_ints(out, limbs) == want, f"{bits}-bit product, single job"
+        one.destroy()
+    for plan in plans:
         plan.destroy()

@@ -1,10 +1,11 @@
 """Element-wise modular BLAS on the GPU against the oracle, bit for bit.
 
 Covers the three widths (60-bit moduli in one limb, 124-bit in two, 225- and
-252-bit in four), lengths that
-are multiples of the kernel's chunk and ragged ones, the paper scale length
-2^16, a long ragged vector spanning 1025 blocks (sampled), every pair of edge residues, exact aliasing (c == a) and
-edge scalars for axpy."""
+252-bit in four), odd moduli at every position of each width class (2 to 252
+bits), lengths that are multiples of the kernel's chunk and ragged ones, the
+paper scale length 2^16, a long ragged vector spanning 1025 blocks (sampled),
+every pair of edge residues, exact aliasing (c == a) and edge scalars for
+axpy."""
 import itertools
 
 import pytest
@@ -156,30 +157,49 @@ def test_sub_range_of_buffer():
     assert got[2049:] == [0] * (3000 - 2049)
 
 
-@pytest.mark.parametrize("bits,seed", [(61, 17), (125, 18), (200, 19)])
-@pytest.mark.parametrize("n", [1, 1000, 4099])
-def test_add_sub_axpy_low_widths(n, bits, seed):
-    """Add, sub and axpy at widths below Barrett's range for their limb class
-    (61 bits in two words, 125 and 200 in four): whole outputs against the
-    oracle; vec_mulmod rejects these widths (checked on the host)."""
+# Odd moduli across every width class, including the low end of each class
+# and widths between the old fixed-offset Barrett ranges: 2-, 14-, 17- and
+# 32-bit values written out (Barrett needs an odd modulus, not a prime), the
+# rest seeded primes.
+FIXED_MODULI = {2: 3, 14: 12289, 17: 65537, 32: (1 << 32) - 5}
+ANY_WIDTH = [2, 14, 17, 32, 33, 59, 60, 61, 80, 96, 97, 123, 124, 125, 160, 200, 224, 225, 251, 252]
+
+
+def _any_modulus(bits):
+    return FIXED_MODULI.get(bits) or prime(bits, 700 + bits)
+
+
+@pytest.mark.parametrize("bits", ANY_WIDTH)
+def test_every_width_edges_and_ragged(bits):
+    """All four ops at every width class position: every pair of edge
+    residues, then a ragged uniform vector (n = 4099) and the 2^16 length,
+    whole outputs against the oracle (Barrett holds for general moduli,
+    Eq. barrett)."""
     require_gpu()
     import torch
-    q = prime(bits, seed)
+    q = _any_modulus(bits)
+    assert q.bit_length() == bits and q % 2 == 1
     limbs = W.limbs_for_bits(bits)
-    g = W.rng(n * 11 + bits)
-    A = W.uniform_residues(g, q, n, limbs)
-    B = W.uniform_residues(g, q, n, limbs)
-    alpha = W.uniform_scalar(g, q, limbs)
-    announce("low width", n, bits)
-    a, b = dev(A), dev(B)
-    for op in ("vec_addmod", "vec_submod"):
-        c = torch.empty_like(a)
-        getattr(mwntt, op)(c, a, b, q, limbs)
-        torch.cuda.synchronize()
-        assert host_ints(c, limbs) == _oracle(op, W.to_ints(A), W.to_ints(B), q), op
-    y = b.clone()
-    mwntt.vec_axpymod(y, alpha, a, q, limbs)
-    torch.cuda.synchronize()
-    assert host_ints(y, limbs) == [(alpha * x + z) % q for x, z in zip(W.to_ints(A), W.to_ints(B))]
-    with pytest.raises(mwntt.MwError):
-        mwntt.vec_mulmod(torch.empty_like(a), a, b, q, limbs)
+    ev = sorted(set(v % q for v in edge_values(q)))
+    pairs = list(itertools.product(ev, ev))
+    a_i = [x for x, _ in pairs]
+    b_i = [y for _, y in pairs]
+    for n, (A, B) in (("edges", (W.from_ints(a_i, limbs), W.from_ints(b_i, limbs))),
+                      (4099, (W.uniform_residues(W.rng(bits), q, 4099, limbs),
+                              W.uniform_residues(W.rng(bits + 1), q, 4099, limbs))),
+                      (1 << 16, (W.uniform_residues(W.rng(bits + 2), q, 1 << 16, limbs),
+                                 W.uniform_residues(W.rng(bits + 3), q, 1 << 16, limbs)))):
+        a, b = dev(A), dev(B)
+        ai, bi = W.to_ints(A), W.to_ints(B)
+        for op in OPS:
+            announce("any width", op, n, bits)
+            c = torch.empty_like(a)
+            getattr(mwntt, op)(c, a, b, q, limbs)
+            torch.cuda.synchronize()
+            assert host_ints(c, limbs) == _oracle(op, ai, bi, q), (op, n)
+        for alpha in (ev if n == "edges" else [W.uniform_scalar(W.rng(bits + 4), q, limbs)]):
+            announce("any width axpy", n, bits)
+            y = b.clone()
+            mwntt.vec_axpymod(y, alpha, a, q, limbs)
+            torch.cuda.synchronize()
+            assert host_ints(y, limbs) == oracle.modarith.vec_axpymod(alpha, ai, bi, q), (alpha, n)

@@ -55,7 +55,7 @@ def test_canonical_root_small_primes():
         assert mwntt.canonical_root(q, 1, log2n) == oracle.roots.canonical_psi(q, n)
 
 
-@pytest.mark.parametrize("bits", [60, 124, 252, 225, 130])
+@pytest.mark.parametrize("bits", [60, 124, 252, 225, 130, 33, 80, 97, 200])
 def test_shoup_and_barrett_constants(bits):
     q = W.find_prime(bits, 77)
     limbs = W.limbs_for_bits(bits)
@@ -63,7 +63,25 @@ def test_shoup_and_barrett_constants(bits):
     ws = W.to_ints(W.uniform_residues(g, q, 50, limbs)) + [0, 1, q - 1]
     for w in ws:
         assert mwntt.shoup_companion(w, q, limbs) == (w << (64 * limbs)) // q
-    assert mwntt.barrett_mu(q, limbs) == (1 << (2 * q.bit_length())) // q
+    # Barrett runs on q scaled to the top of its width class (T bits)
+    T = {1: 60, 2: 124, 4: 252}[limbs]
+    qn = q << (T - bits)
+    assert qn.bit_length() == T
+    assert mwntt.barrett_mu(q, limbs) == (1 << (2 * T)) // qn
+
+
+def test_barrett_constant_small_moduli():
+    for q in (3, 5, 12289, 65537, (1 << 32) - 5):
+        qn = q << (60 - q.bit_length())
+        assert mwntt.barrett_mu(q, 1) == (1 << 120) // qn
+
+
+def test_validate_mode_switch_without_device():
+    # off by default (MWNTT_VALIDATE unset); turning it off needs no device
+    assert mwntt.get_validate() is False
+    mwntt.set_validate(False)
+    assert mwntt.get_validate() is False
+    assert mwntt.status_str(mwntt.MW_ENONCANON).startswith("input residue not canonical")
 
 
 def test_argument_errors_without_device():
@@ -102,16 +120,9 @@ def test_argument_errors_without_device():
         mwntt.vec_mulmod(8, 8, 8, (1 << 40) + 1 - 2**20, 2, n=5, stream=0)   # width mismatch
     assert e.value.status == -2
     with pytest.raises(mwntt.MwError) as e:
-        mwntt.vec_mulmod(8, 8, 8, 12289, 1, n=5, stream=0)  # Barrett needs >= 33 bits
-    assert e.value.status == -2
-    with pytest.raises(mwntt.MwError) as e:
         mwntt.vec_axpymod(8, q60, 8, q60, 1, n=5, stream=0)  # alpha not reduced
     assert e.value.status == -1
-    # four-word moduli: 125..252 bits, Barrett from 225 bits
-    q200 = W.find_prime(200, 6004)
-    with pytest.raises(mwntt.MwError) as e:
-        mwntt.vec_mulmod(8, 8, 8, q200, 4, n=5, stream=0)
-    assert e.value.status == -2
+    # four-word moduli: 125..252 bits
     with pytest.raises(mwntt.MwError) as e:
         mwntt.ntt_plan(10, q124, 4)                 # 124-bit q in four limbs
     assert e.value.status == -2

@@ -17,14 +17,17 @@ OPS = [mwntt.MW_REQ_NTT_FORWARD, mwntt.MW_REQ_NTT_INVERSE, mwntt.MW_REQ_POLYMUL,
        mwntt.MW_REQ_VEC_MULMOD, mwntt.MW_REQ_VEC_AXPYMOD, mwntt.MW_REQ_VEC_ADDMOD, mwntt.MW_REQ_VEC_SUBMOD]
 
 
-def _workload(count, seed, log2_range=(10, 13), wide=False):
+def _workload(count, seed, log2_range=(10, 13), wide=False, widths=None):
     import torch
     g = W.rng(seed)
     plans = {}
     items = []
     for i in range(count):
         op = OPS[i % len(OPS)]
-        bits = [60, 124, 252][int(g.integers(0, 3))] if wide else (60 if g.random() < 0.5 else 124)
+        if widths:
+            bits = widths[int(g.integers(0, len(widths)))]
+        else:
+            bits = [60, 124, 252][int(g.integers(0, 3))] if wide else (60 if g.random() < 0.5 else 124)
         q = prime(bits, 61 + (i % 2))
         limbs = W.limbs_for_bits(bits)
         if op <= mwntt.MW_REQ_POLYMUL:
@@ -176,6 +179,30 @@ def test_one_request_at_a_time_matches_alone():
             assert [got[k] for k in ks] == _oracle_sample(it, ks), f"request {i}"
     st = srv.stats()
     assert st["completed"] == len(items) and st["max_batch_seen"] == 1
+    srv.destroy()
+    for p in plans.values():
+        p.destroy()
+
+
+def test_mixed_stream_odd_widths():
+    """A batched stream at widths inside each class (33, 80, 97, 200 and 251
+    bits: Barrett on the scaled modulus in products and vec_mulmod): every
+    result equals the same operation alone, and samples equal the oracle."""
+    require_gpu()
+    import torch
+    items, plans = _workload(35, seed=47, log2_range=(6, 11), widths=[33, 80, 97, 200, 251])
+    srv = mwntt.MwServer(1 << 30, max_inflight=3, max_batch=16)
+    announce("serve odd widths", len(items))
+    tickets = [srv.submit(_request(it)) for it in items]
+    for i, (t, it) in enumerate(zip(tickets, items)):
+        ptr, _ = srv.result(t, wait=True)
+        out = mwntt.copy_to_tensor(ptr, it["a"])
+        torch.cuda.synchronize()
+        srv.release(t)
+        assert torch.equal(out, _alone(it)), f"request {i} op {it['op']} bits {it['q'].bit_length()}"
+        ks = [0, it["n"] - 1, (i * 37) % it["n"]]
+        got = host_ints(out, it["limbs"])
+        assert [got[k] for k in ks] == _oracle_sample(it, ks), f"request {i}"
     srv.destroy()
     for p in plans.values():
         p.destroy()
