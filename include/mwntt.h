@@ -182,6 +182,21 @@ int ntt_inverse(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, 
  * single-workgroup transform; MW_ESIZE if the batch exceeds the scratch. */
 int ntt_forward_pass(ntt_plan_t plan, uint32_t pass, void* d_out, const void* d_in, uint32_t batch, void* stream);
 
+/* Allocation-free transform, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): ntt_forward (inverse == 0) or ntt_inverse (inverse == 1) with
+ * the same arguments and results, except that the two-pass intermediate lives
+ * in a static 64 MiB device array that the library holds on each device it
+ * runs on until the process ends, instead of the plan's scratch.  The call
+ * allocates nothing and needs no plan scratch; the array's device address is
+ * looked up on the first call on each device.  MW_ESIZE if a two-pass call's
+ * intermediate (batch * N * limbs * 8 bytes) exceeds 64 MiB, e.g. more than
+ * 32 two-word transforms of 2^16 points (single-workgroup sizes have no
+ * limit).  Calls that overlap in time on one device share the array and race;
+ * serialize them (one stream, or events).  Not covered by validate mode. */
+int ntt_transform_noalloc(ntt_plan_t plan, uint32_t inverse, void* d_out, const void* d_in, uint32_t batch,
+                          void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched executor: many jobs -- forward or inverse transforms, or fused     */
 /* negacyclic products c = INTT(NTT(a) * NTT(b)) (Background, polynomial     */

@@ -9,6 +9,7 @@
 // mw_ntt_tile.h (see the algorithm notes there).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -184,8 +185,11 @@ const PlanConfig& pick_config(const ntt_plan_s* P, uint32_t batch) {
   return ((uint64_t)batch << P->log2n) >= kThroughputResidues ? P->thr : P->lat;
 }
 
+// scratch / chunk: the two-pass intermediate and the polynomials it holds
+// (the plan's own buffer, or the static one of ntt_transform_noalloc).
 template <int W>
-int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, int dir, hipStream_t s) {
+int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, int dir, hipStream_t s,
+                  void* scratch, uint32_t chunk) {
   NttParams<W> p = {};
   p.tw = reinterpret_cast<const Tw<W>*>(dir == DIR_FWD ? P->d_tw_fwd : P->d_tw_inv);
   if constexpr (W == 8) {
@@ -217,12 +221,11 @@ int run_transform(ntt_plan_s* P, void* d_out, const void* d_in, uint32_t batch, 
   }
   const u32 col_tiles = tiles_per_poly<MODE_COL>(P->log2n, C.log_n1, C.cfg[MODE_COL].lines);
   const u32 row_tiles = tiles_per_poly<MODE_ROW>(P->log2n, C.log_n1, C.cfg[MODE_ROW].lines);
-  const uint32_t chunk = P->scratch_polys;
   for (uint32_t b0 = 0; b0 < batch; b0 += chunk) {
     const uint32_t nb = (batch - b0 < chunk) ? batch - b0 : chunk;
     const Res<W>* in = reinterpret_cast<const Res<W>*>(d_in) + (uint64_t)b0 * N;
     Res<W>* out = reinterpret_cast<Res<W>*>(d_out) + (uint64_t)b0 * N;
-    Res<W>* scr = reinterpret_cast<Res<W>*>(P->d_scratch);
+    Res<W>* scr = reinterpret_cast<Res<W>*>(scratch);
     p.batch = nb;
     if (dir == DIR_FWD) {
       p.src = in;
@@ -267,9 +270,9 @@ int transform(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, vo
   const int vs = validate_polys(plan, d_in, batch, s);
   if (vs != MW_OK) return vs;
   switch (plan->limbs) {
-    case 4: return run_transform<8>(plan, d_out, d_in, batch, dir, s);
-    case 2: return run_transform<4>(plan, d_out, d_in, batch, dir, s);
-    default: return run_transform<2>(plan, d_out, d_in, batch, dir, s);
+    case 4: return run_transform<8>(plan, d_out, d_in, batch, dir, s, plan->d_scratch, plan->scratch_polys);
+    case 2: return run_transform<4>(plan, d_out, d_in, batch, dir, s, plan->d_scratch, plan->scratch_polys);
+    default: return run_transform<2>(plan, d_out, d_in, batch, dir, s, plan->d_scratch, plan->scratch_polys);
   }
 }
 
@@ -616,4 +619,64 @@ extern "C" int ntt_forward(ntt_plan_t plan, void* d_out, const void* d_in, uint3
 
 extern "C" int ntt_inverse(ntt_plan_t plan, void* d_out, const void* d_in, uint32_t batch, void* stream) {
   return transform(plan, d_out, d_in, batch, stream, DIR_INV);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free transforms
+// ---------------------------------------------------------------------------
+// For callers that cannot allocate (code under stream capture, tight serving
+// loops): the two-pass intermediate lives in a file-scope device array of
+// kStaticScratchBytes that each device holds for the life of the process.  Its
+// device address is looked up once per device (hipGetSymbolAddress with that
+// device current) and only that address is used from host code; the symbol
+// itself is not a device pointer on the host.  Every call on one device shares
+// the array: calls that overlap in time on one device race.  Nothing in it
+// needs clearing (the first pass writes every element the second reads).
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on first use).
+int static_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MW_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MW_EDEVICE;
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return MW_OK;
+}
+}  // namespace
+
+extern "C" int ntt_transform_noalloc(ntt_plan_t plan, uint32_t inverse, void* d_out, const void* d_in,
+                                     uint32_t batch, void* stream) {
+  if (!plan || inverse > 1) return MW_EINVAL;
+  if (batch == 0) return MW_OK;
+  if (!d_out || !d_in) return MW_EINVAL;
+  const int dir = inverse ? DIR_INV : DIR_FWD;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const PlanConfig& C = pick_config(plan, batch);
+  void* scr = nullptr;
+  uint32_t chunk = batch;
+  if (C.log_n1) {
+    const uint64_t need = ((uint64_t)batch * 8 * plan->limbs) << plan->log2n;
+    if (need > kStaticScratchBytes) return MW_ESIZE;
+    const int st = static_scratch(&scr);
+    if (st != MW_OK) return st;
+  }
+  switch (plan->limbs) {
+    case 4: return run_transform<8>(plan, d_out, d_in, batch, dir, s, scr, chunk);
+    case 2: return run_transform<4>(plan, d_out, d_in, batch, dir, s, scr, chunk);
+    default: return run_transform<2>(plan, d_out, d_in, batch, dir, s, scr, chunk);
+  }
 }

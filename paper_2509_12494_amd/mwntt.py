@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
         "ntt_forward": (ctypes.c_int, [vp, vp, vp, u32, vp]),
         "ntt_forward_pass": (ctypes.c_int, [vp, u32, vp, vp, u32, vp]),
         "ntt_inverse": (ctypes.c_int, [vp, vp, vp, u32, vp]),
+        "ntt_transform_noalloc": (ctypes.c_int, [vp, u32, vp, vp, u32, vp]),
         "ntt_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(NttJob), u32]),
         "ntt_batch_run": (ctypes.c_int, [vp, vp]),
         "ntt_batch_info": (ctypes.c_int, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
@@ -315,6 +316,12 @@ class NttPlan:
         else:
             st = L.ntt_inverse(self._h, _ptr(out), _ptr(inp), b, _stream(stream))
         _check(st, "ntt_inverse")
+
+    def transform_noalloc(self, inverse: bool, out, inp, batch: Optional[int] = None, stream=None) -> None:
+        """ntt_transform_noalloc: forward or inverse with the library's static scratch (no allocation)."""
+        b = self._batch(inp, batch)
+        _check(lib().ntt_transform_noalloc(self._h, 1 if inverse else 0, _ptr(out), _ptr(inp), b, _stream(stream)),
+               "ntt_transform_noalloc")
 
     def destroy(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
