@@ -155,6 +155,10 @@ int ntt_plan_root(ntt_plan_t plan, uint64_t* psi_out);
  * configuration.  Not thread-safe with concurrent transforms on the plan. */
 int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1);
 int ntt_plan_get_split(ntt_plan_t plan, uint32_t* log_n1);
+/* The configuration a call with `batch` transforms runs: *large = 1 for the
+ * large-batch one (0 for the single-transform one, or when a split or shape
+ * was set), *log_n1 its split. */
+int ntt_plan_config_for(ntt_plan_t plan, uint32_t batch, uint32_t* large, uint32_t* log_n1);
 
 /* Tile shape of one pass (pass 0: single-workgroup transform, 1: column pass,
  * 2: row pass): 2^log_p points per lane (1 <= log_p <= 4; <= 2 for four-word

@@ -78,6 +78,11 @@ __device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
 __device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
 __device__ __forceinline__ u64 pack(u32 lo, u32 hi) { return ((u64)hi << 32) | lo; }
 
+// The three instruction wrappers below are the only CDNA-specific code of the
+// arithmetic.  An includer that defines MW_ISA_EMULATED supplies its own
+// mad_cc / add_carry / funnel with the same contracts (the CPU emulation test
+// does, to run this header's routines on the host).
+#ifndef MW_ISA_EMULATED
 // acc = a*b + acc (mod 2^64); returns the carry-out lane mask.
 __device__ __forceinline__ u64 mad_cc(u32 a, u32 b, u64& acc) {
   u64 cc;
@@ -92,6 +97,10 @@ __device__ __forceinline__ u32 add_carry(u32 x, u64 cc) {
   asm("v_addc_co_u32 %0, %1, %2, 0, %3" : "=v"(d), "=s"(co) : "v"(x), "s"(cc));
   return d;
 }
+
+// funnel shift: bits [s, s+32) of the 64-bit value hi:lo, 0 <= s < 32
+__device__ __forceinline__ u32 funnel(u32 hi, u32 lo, u32 s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
+#endif
 
 // plain a*b + c, no carry needed (caller guarantees no overflow, or only
 // the result modulo 2^64 is used)
@@ -484,9 +493,6 @@ __device__ __forceinline__ Res<W> shoup_mul(const Res<W>& x, const u32 (&w)[W], 
   Res<W> Q = mul_hi_est(x, ws);
   return mul_lo2(x, w, Q, M.negq);
 }
-
-// funnel shift: bits [s, s+32) of the 64-bit value hi:lo, 0 <= s < 32
-__device__ __forceinline__ u32 funnel(u32 hi, u32 lo, u32 s) { return __builtin_amdgcn_alignbit(hi, lo, s); }
 
 // Word moves of the uniform shifts: by K, 2K, 4K, ... words where the
 // corresponding bit of ws is set, as selects (every index a compile-time

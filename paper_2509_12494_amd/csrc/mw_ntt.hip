@@ -594,6 +594,14 @@ extern "C" int ntt_plan_get_tiles(ntt_plan_t plan, uint32_t pass, uint32_t* log_
   return MW_OK;
 }
 
+extern "C" int ntt_plan_config_for(ntt_plan_t plan, uint32_t batch, uint32_t* large, uint32_t* log_n1) {
+  if (!plan || !large || !log_n1) return MW_EINVAL;
+  const PlanConfig& C = pick_config(plan, batch);
+  *large = (!plan->forced && &C == &plan->thr) ? 1u : 0u;
+  *log_n1 = C.log_n1;
+  return MW_OK;
+}
+
 extern "C" int ntt_plan_get_split(ntt_plan_t plan, uint32_t* log_n1) {
   if (!plan || !log_n1) return MW_EINVAL;
   *log_n1 = visible_config(plan).log_n1;

@@ -43,14 +43,9 @@
 #include <hip/hip_runtime.h>
 
 #include "mw_arith.h"
+#include "mw_butterfly.h"
 
 namespace mw {
-
-template <int W>
-struct Tw {
-  u32 w[W];
-  u32 ws[W];
-};
 
 template <int W>
 __device__ __forceinline__ Tw<W> load_tw(const Tw<W>* t, u32 idx) {
@@ -93,49 +88,6 @@ struct NttParams {
   u32 lines;             // lines per tile (a power of two)
   u32 pad_[3];
 };
-
-// Forward (Cooley-Tukey) butterfly on [0, 16q) values.
-template <int W>
-__device__ __forceinline__ void ct_bfly(Res<W>& X, Res<W>& Y, const Tw<W>& t, const Modulus<W>& M) {
-  Res<W> T = shoup_mul(Y, t.w, t.ws, M);   // [0, 6q)
-  Res<W> Xr = csub(X, M.q8);               // [0, 8q)
-  X = add(Xr, T);                          // [0, 14q)
-  Res<W> D = add(Xr, M.q8);                // [8q, 16q)
-  u32 b;
-  Y = sub(D, T, b);                        // (2q, 16q)
-}
-
-// Inverse (Gentleman-Sande) butterfly on [0, 8q) values.
-template <int W>
-__device__ __forceinline__ void gs_bfly(Res<W>& X, Res<W>& Y, const Tw<W>& t, const Modulus<W>& M) {
-  Res<W> S = csub(add(X, Y), M.q8);        // [0, 8q)
-  Res<W> D = add(X, M.q8);
-  u32 b;
-  D = sub(D, Y, b);                        // (0, 16q)
-  Y = shoup_mul(D, t.w, t.ws, M);          // [0, 6q)
-  X = S;
-}
-
-// Last inverse stage with N^-1 folded in; outputs canonical.
-template <int W>
-__device__ __forceinline__ void gs_bfly_last(Res<W>& X, Res<W>& Y, const Tw<W>& ninv, const Tw<W>& ninv_w1,
-                                             const Modulus<W>& M) {
-  Res<W> S = add(X, Y);                    // [0, 16q) < 2^(32W)
-  Res<W> D = add(X, M.q8);
-  u32 b;
-  D = sub(D, Y, b);                        // (0, 16q)
-  Res<W> x = shoup_mul(S, ninv.w, ninv.ws, M);     // [0, 6q)
-  Res<W> y = shoup_mul(D, ninv_w1.w, ninv_w1.ws, M);
-  x = csub(csub(csub(x, M.q4), M.q2), M.q);
-  y = csub(csub(csub(y, M.q4), M.q2), M.q);
-  X = x;
-  Y = y;
-}
-
-template <int W>
-__device__ __forceinline__ Res<W> canon16(const Res<W>& x, const Modulus<W>& M) {
-  return csub(csub(csub(csub(x, M.q8), M.q4), M.q2), M.q);
-}
 
 __device__ __forceinline__ u32 brev(u32 x, u32 bits) {
   return bits ? (__builtin_bitreverse32(x) >> (32 - bits)) : 0u;
@@ -196,6 +148,25 @@ __device__ __forceinline__ u32 pad_idx(u32 j) {
   else return j;
 }
 
+// Ordering between the rounds of a line.  The lanes of one line exchange
+// points through the line's LDS slots; a line held by at most one wavefront
+// (2^(LOGL - LOGP) <= 64 lanes, lines never straddle wavefronts) is private to
+// that wavefront, whose LDS accesses execute in order, so the rounds only need
+// the compiler kept from moving LDS accesses across the boundary (a
+// wavefront-scope fence and barrier) instead of a workgroup barrier.  Longer
+// lines, and the end of the last round (the tile's copy-out, or a fused
+// product's point-wise step, reads across lines), take __syncthreads.
+template <int TPL>
+__device__ __forceinline__ void round_sync(bool last) {
+  if (TPL <= 64 && !last) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One round of a line: LOGP (or, for round 0, the remainder P0) stages on the
 // P points a lane holds, between an LDS load and an LDS store.  In round r the
 // lane's point u sits at line index base_j | (u << L0), L0 = LOGL - s0 - LOGP;
@@ -240,7 +211,7 @@ struct Round {
   }
 
   static __device__ __forceinline__ void run(Res<W>* line, u32 tid, u32 base, const Tw<W>* __restrict__ tw,
-                                             const NttParams<W>& p, bool last_inv, bool canon) {
+                                             const NttParams<W>& p, bool last_inv, bool canon, bool last_round) {
     const u32 base_j = ((tid >> L0) << (L0 + LOGP)) | (tid & ((1u << L0) - 1u));
     Res<W> x[P];
 #pragma unroll
@@ -252,7 +223,7 @@ struct Round {
     }
 #pragma unroll
     for (int u = 0; u < P; ++u) line[pad_idx<LOGL, LOGP>(base_j | ((u32)u << L0))] = x[u];
-    __syncthreads();
+    round_sync<S::TPL>(last_round);
   }
 };
 
@@ -266,7 +237,7 @@ __device__ __forceinline__ void line_stages(Res<W>* line, u32 tid, u32 base, con
   using S = LineShape<LOGL, LOGP>;
   constexpr int R = (DIR == DIR_FWD) ? RR : (S::R - 1 - RR);
   Round<W, LOGL, LOGP, DIR, R>::run(line, tid, base, tw, p, last_inv,
-                                    DIR == DIR_FWD && final_fwd && RR == S::R - 1);
+                                    DIR == DIR_FWD && final_fwd && RR == S::R - 1, RR == S::R - 1);
   if constexpr (RR + 1 < S::R) line_stages<W, LOGL, LOGP, DIR, RR + 1>(line, tid, base, tw, p, last_inv, final_fwd);
 }
 

@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
         "ntt_forward_pass": (ctypes.c_int, [vp, u32, vp, vp, u32, vp]),
         "ntt_inverse": (ctypes.c_int, [vp, vp, vp, u32, vp]),
         "ntt_transform_noalloc": (ctypes.c_int, [vp, u32, vp, vp, u32, vp]),
+        "ntt_plan_config_for": (ctypes.c_int, [vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
         "ntt_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(NttJob), u32]),
         "ntt_batch_run": (ctypes.c_int, [vp, vp]),
         "ntt_batch_info": (ctypes.c_int, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32)]),
@@ -283,6 +284,12 @@ class NttPlan:
         lp, ln = ctypes.c_uint32(), ctypes.c_uint32()
         _check(lib().ntt_plan_get_tiles(self._h, pass_, ctypes.byref(lp), ctypes.byref(ln)), "ntt_plan_get_tiles")
         return lp.value, ln.value
+
+    def config_for(self, batch: int):
+        """(large-batch configuration?, log2 N1) of a call with `batch` transforms."""
+        lg, l1 = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().ntt_plan_config_for(self._h, batch, ctypes.byref(lg), ctypes.byref(l1)), "ntt_plan_config_for")
+        return bool(lg.value), l1.value
 
     def _batch(self, t, batch):
         if batch is not None:

@@ -4,9 +4,11 @@
     python -m paper_2509_12494_amd.profile_summary kernels RESULTS.db [--match mw::] [--top N]
     python -m paper_2509_12494_amd.profile_summary counters FETCH.db WRITE.db --copy-bytes BYTES [--match mw::] [--top N]
     python -m paper_2509_12494_amd.profile_summary valu VALU.db [--match mw::] [--top N]
+    python -m paper_2509_12494_amd.profile_summary sq A.db [B.db ...] [--match mw::]
 
 `kernels` lists every kernel (grouped by name and grid size) with its launch
-count and average / min / max duration.  `counters` reads FETCH_SIZE and
+count and average / min / max duration.  `sq` lists every counter of one or more counter runs per kernel (name, grid
+size), averaged over dispatches.  `counters` reads FETCH_SIZE and
 WRITE_SIZE (KiB per dispatch) from two separate counter runs and converts them
 to bytes with the factor that makes the largest single device-to-device copy
 dispatch of the run (`__amd_rocclr_copyBuffer`, BYTES long) read and write
@@ -91,6 +93,20 @@ def valu(db, match=None):
     return out
 
 
+def sq(dbs, match=None):
+    """{(kernel, workgroups): {counter: (average per dispatch, dispatches)}} over several runs."""
+    rows = {}
+    for db in dbs:
+        con = sqlite3.connect(db)
+        q = ("select kernel_name, grid_size, workgroup_size, counter_name, avg(value), count(*) "
+             "from counters_collection group by kernel_name, grid_size, counter_name")
+        for k, g, w, c, v, n in con.execute(q):
+            if match and match not in k:
+                continue
+            rows.setdefault((_short(k), g // max(w, 1)), {})[c] = (v, n)
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -108,7 +124,20 @@ def main(argv=None):
     c.add_argument("db")
     c.add_argument("--match", default=None)
     c.add_argument("--top", type=int, default=None)
+    d = sub.add_parser("sq")
+    d.add_argument("dbs", nargs="+")
+    d.add_argument("--match", default=None)
     args = ap.parse_args(argv)
+    if args.cmd == "sq":
+        rows = sq(args.dbs, args.match)
+        names = sorted({c for r in rows.values() for c in r})
+        print("| kernel | workgroups | dispatches | " + " | ".join(names) + " |")
+        print("|---|---|---|" + "---|" * len(names))
+        for (k, g), r in sorted(rows.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+            n = max(v[1] for v in r.values())
+            vals = " | ".join(f"{r[c][0]:.0f}" if c in r else "" for c in names)
+            print(f"| `{k}` | {g} | {n} | {vals} |")
+        return 0
     if args.cmd == "kernels":
         print("| kernel | workgroups | threads | launches | avg us | min us | max us |")
         print("|---|---|---|---|---|---|---|")
