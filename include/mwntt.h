@@ -107,6 +107,13 @@ int vec_submod(void* d_c, const void* d_a, const void* d_b, size_t n,
 /* Point-wise product reduced with Barrett's method (Eq. barrett). */
 int vec_mulmod(void* d_c, const void* d_a, const void* d_b, size_t n,
                const uint64_t* q, uint32_t limbs, void* stream);
+/* Product kernel of vec_mulmod for one width (limbs 1, 2 or 4): karatsuba = 1
+ * forms the full product of the Barrett reduction by one level of Karatsuba
+ * (Eq. mulk; three half-size products and the carry corrections), 0 by the
+ * schoolbook columns (Eq. muls).  Results are identical; the default per width
+ * is the measured faster one.  Process-wide, applies to later calls. */
+int vec_mulmod_set_product(uint32_t limbs, uint32_t karatsuba);
+int vec_mulmod_get_product(uint32_t limbs, uint32_t* karatsuba);
 /* y[i] = (alpha * x[i] + y[i]) mod q; alpha is `limbs` host words, < q. */
 int vec_axpymod(void* d_y, const uint64_t* alpha, const void* d_x, size_t n,
                 const uint64_t* q, uint32_t limbs, void* stream);

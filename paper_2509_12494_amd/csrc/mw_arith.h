@@ -412,6 +412,65 @@ __device__ __forceinline__ void mul_cols(const u32 (&a)[W], const u32 (&b)[W], u
   out[2 * W - 1 - C0] = hi32(acc);
 }
 
+// Full 2W-word product by one level of Karatsuba (Eq. mulk) on W/2-word
+// halves a = a1*B + a0, b = b1*B + b0, B = 2^(16W):
+//   a*b = z2*B^2 + z1*B + z0, z0 = a0*b0, z2 = a1*b1,
+//   z1 = (a0 + a1)(b0 + b1) - z0 - z2 = a0*b1 + a1*b0 < 2*B^2.
+// The half sums carry one bit each (ca, cb), so the middle product is
+// m + (ca*sb + cb*sa)*B + ca*cb*B^2 with m = sa*sb; three half products of
+// (W/2)^2 word products replace the W^2 of the schoolbook product, at the
+// price of the half sums, the carry corrections and the two subtractions.
+template <int W>
+__device__ __forceinline__ void mul_full_kara(const u32 (&a)[W], const u32 (&b)[W], u32 (&r)[2 * W]) {
+  constexpr int H = W / 2;
+  u32 a0[H], a1[H], b0[H], b1[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    a0[i] = a[i];
+    a1[i] = a[H + i];
+    b0[i] = b[i];
+    b1[i] = b[H + i];
+  }
+  u32 z0[2 * H], z2[2 * H], m[2 * H];
+  mul_cols<H, 0>(a0, b0, z0);
+  mul_cols<H, 0>(a1, b1, z2);
+  u32 sa[H], sb[H], ca = 0, cb = 0;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    sa[i] = __builtin_addc(a0[i], a1[i], ca, &ca);
+    sb[i] = __builtin_addc(b0[i], b1[i], cb, &cb);
+  }
+  mul_cols<H, 0>(sa, sb, m);
+  // middle product, 2H + 1 words: m + (ca ? sb : 0)*B + (cb ? sa : 0)*B + ca*cb*B^2
+  const u32 ma = 0u - ca, mb = 0u - cb;
+  u32 top = ca & cb, c1 = 0, c2 = 0;
+#pragma unroll
+  for (int i = 0; i < H; ++i) m[H + i] = __builtin_addc(m[H + i], sb[i] & ma, c1, &c1);
+#pragma unroll
+  for (int i = 0; i < H; ++i) m[H + i] = __builtin_addc(m[H + i], sa[i] & mb, c2, &c2);
+  top += c1 + c2;
+  // z1 = middle - z0 - z2 (non-negative, below 2^(64H+1))
+  u32 d1 = 0, d2 = 0;
+#pragma unroll
+  for (int i = 0; i < 2 * H; ++i) m[i] = __builtin_subc(m[i], z0[i], d1, &d1);
+  top -= d1;
+#pragma unroll
+  for (int i = 0; i < 2 * H; ++i) m[i] = __builtin_subc(m[i], z2[i], d2, &d2);
+  top -= d2;
+  // r = z2*B^2 + z0, plus z1 at word H (the sum is below 2^(64W): no carry out)
+#pragma unroll
+  for (int i = 0; i < 2 * H; ++i) {
+    r[i] = z0[i];
+    r[2 * H + i] = z2[i];
+  }
+  u32 c = 0;
+#pragma unroll
+  for (int i = 0; i < 2 * H; ++i) r[H + i] = __builtin_addc(r[H + i], m[i], c, &c);
+  r[3 * H] = __builtin_addc(r[3 * H], top, c, &c);
+#pragma unroll
+  for (int i = 3 * H + 1; i < 2 * W; ++i) r[i] = __builtin_addc(r[i], 0u, c, &c);
+}
+
 // Low W words of a*b (+ c*d when TWO) (columns 0..W-1; column W-2 is only
 // needed modulo 2^64 and column W-1 modulo 2^32).
 template <int W, bool TWO>
@@ -547,9 +606,11 @@ __device__ __forceinline__ Res<W> shr_uniform(const Res<W>& a, u32 s) {
 // Barrett core on the normalised modulus (T = 124 bits): canonical x mod q'
 // for x = a*b < 2^248.  The shifts by T - 1 = 123 and T + 1 = 125 bits start
 // in word 3 at bit offsets 27 and 29.
+template <bool KARA = false>
 __device__ __forceinline__ Res<4> barrett_core(const Res<4>& a, const Res<4>& b, const Modulus<4>& M) {
   u32 x[8];
-  mul_full(a, b, x);
+  if constexpr (KARA) mul_full_kara<4>(a.v, b.v, x);
+  else mul_full(a, b, x);
   constexpr u32 s1 = (barrett_bits<4>() - 1) & 31;
   Res<4> q1;
   q1.v[0] = funnel(x[4], x[3], s1);
@@ -612,9 +673,11 @@ __device__ __forceinline__ Res<4> barrett_core(const Res<4>& a, const Res<4>& b,
 }
 
 // T = 60 bits: the shifts by 59 and 61 bits start in word 1.
+template <bool KARA = false>
 __device__ __forceinline__ Res<2> barrett_core(const Res<2>& a, const Res<2>& b, const Modulus<2>& M) {
   u32 x[4];
-  mul_full(a, b, x);
+  if constexpr (KARA) mul_full_kara<2>(a.v, b.v, x);
+  else mul_full(a, b, x);
   constexpr u32 s1 = (barrett_bits<2>() - 1) & 31;
   Res<2> q1;
   q1.v[0] = funnel(x[2], x[1], s1);
@@ -640,9 +703,11 @@ __device__ __forceinline__ Res<2> barrett_core(const Res<2>& a, const Res<2>& b,
 // T = 252 bits: the shifts by 251 and 253 bits start in word 7; q1*mu drops
 // columns 0..4 (less than 5 * 2^192 * (1 + 2^-32) < 2^(T+1)), so q3 is at
 // most 3 below floor(x/q') and r < 4q'.
+template <bool KARA = false>
 __device__ __forceinline__ Res<8> barrett_core(const Res<8>& a, const Res<8>& b, const Modulus<8>& M) {
   u32 x[16];
-  mul_cols<8, 0>(a.v, b.v, x);
+  if constexpr (KARA) mul_full_kara<8>(a.v, b.v, x);
+  else mul_cols<8, 0>(a.v, b.v, x);
   constexpr u32 s1 = (barrett_bits<8>() - 1) & 31;
   Res<8> q1;
 #pragma unroll
@@ -667,10 +732,13 @@ __device__ __forceinline__ Res<8> barrett_core(const Res<8>& a, const Res<8>& b,
 // class.  a*2^s < q' and b < q <= q', so x = a*2^s*b < 2^(2T).  NORM (known
 // at compile time) selects the scaled form (M.shift > 0) or the plain one
 // (M.shift == 0); barrett_mul decides at run time with a uniform branch.
-template <int W, bool NORM>
+// KARA: the full product a*b by one level of Karatsuba instead of the
+// schoolbook columns (the other two products of the reduction are truncated,
+// and stay schoolbook).
+template <int W, bool NORM, bool KARA = false>
 __device__ __forceinline__ Res<W> barrett_mul_t(const Res<W>& a, const Res<W>& b, const Modulus<W>& M) {
-  if constexpr (NORM) return shr_uniform(barrett_core(shl_uniform(a, M.shift), b, M), M.shift);
-  else return barrett_core(a, b, M);
+  if constexpr (NORM) return shr_uniform(barrett_core<KARA>(shl_uniform(a, M.shift), b, M), M.shift);
+  else return barrett_core<KARA>(a, b, M);
 }
 
 template <int W>

@@ -18,7 +18,10 @@
 
 #include "mw_arith.h"
 #include "mw_common.h"
+#include "mw_tuned.h"
 #include "mw_validate.h"
+
+#include <atomic>
 
 namespace mw {
 
@@ -32,7 +35,8 @@ struct Scalar {
 
 // NORM: products reduce on the scaled modulus (a modulus below the top of its
 // width class; a kernel of its own, so the full-width one keeps its code).
-template <int W, int OP, bool NORM>
+// KARA: the full product by one level of Karatsuba (Eq. mulk).
+template <int W, int OP, bool NORM, bool KARA = false>
 __device__ __forceinline__ Res<W> blas_elem(const Res<W>& a, const Res<W>& b, const Modulus<W>& M,
                                            const Scalar<W>& s) {
   if constexpr (OP == OP_ADD) {
@@ -40,7 +44,7 @@ __device__ __forceinline__ Res<W> blas_elem(const Res<W>& a, const Res<W>& b, co
   } else if constexpr (OP == OP_SUB) {
     return submod(a, b, M);
   } else if constexpr (OP == OP_MUL) {
-    return barrett_mul_t<W, NORM>(a, b, M);
+    return barrett_mul_t<W, NORM, KARA>(a, b, M);
   } else {
     // a = x, b = y: alpha*x in [0, 6q), + y in [0, 7q) -> canonical
     Res<W> t = shoup_mul(a, s.w, s.ws, M);
@@ -83,7 +87,7 @@ struct Stream<4> {
   }
 };
 
-template <int W, int OP, int VEC, bool NORM>
+template <int W, int OP, int VEC, bool NORM, bool KARA>
 __global__ __launch_bounds__(256) void blas_kernel(Res<W>* c, const Res<W>* a,
                                                    const Res<W>* b, u64 n, Modulus<W> M,
                                                    Scalar<W> s) {
@@ -98,16 +102,32 @@ __global__ __launch_bounds__(256) void blas_kernel(Res<W>* c, const Res<W>* a,
       y[v] = Stream<W>::load(b + base + (u64)v * blockDim.x);
     }
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) Stream<W>::store(c + base + (u64)v * blockDim.x, blas_elem<W, OP, NORM>(x[v], y[v], M, s));
+    for (int v = 0; v < VEC; ++v) Stream<W>::store(c + base + (u64)v * blockDim.x, blas_elem<W, OP, NORM, KARA>(x[v], y[v], M, s));
   }
   // ragged tail: residues [nfull*chunk, n), handled by the one block whose
   // turn comes next in the grid-stride order
   if (blockIdx.x == (unsigned)(nfull % gridDim.x)) {
     for (u64 i = nfull * chunk + threadIdx.x; i < n; i += blockDim.x) {
       Res<W> x = ResIO<W>::load(a + i), y = ResIO<W>::load(b + i);
-      ResIO<W>::store(c + i, blas_elem<W, OP, NORM>(x, y, M, s));
+      ResIO<W>::store(c + i, blas_elem<W, OP, NORM, KARA>(x, y, M, s));
     }
   }
+}
+
+// Product kernel of vec_mulmod per width (index: limbs 1, 2, 4 -> 0, 1, 2):
+// 0 schoolbook, 1 Karatsuba.  Starts from the measured choice (mw_tuned.h);
+// vec_mulmod_set_product changes it for later calls.
+std::atomic<uint32_t> g_kara[3] = {{tuned_karatsuba(1)}, {tuned_karatsuba(2)}, {tuned_karatsuba(4)}};
+
+inline int width_slot(uint32_t limbs) { return limbs == 1 ? 0 : (limbs == 2 ? 1 : (limbs == 4 ? 2 : -1)); }
+
+template <int W, int OP, bool NORM, bool KARA>
+static void launch_blas_kernel(unsigned grid, hipStream_t stream, void* d_c, const void* d_a, const void* d_b,
+                               size_t n, const Modulus<W>& M, const Scalar<W>& s) {
+  constexpr int VEC = 4;
+  hipLaunchKernelGGL((blas_kernel<W, OP, VEC, NORM, KARA>), dim3(grid), dim3(256), 0, stream,
+                     reinterpret_cast<Res<W>*>(d_c), reinterpret_cast<const Res<W>*>(d_a),
+                     reinterpret_cast<const Res<W>*>(d_b), (u64)n, M, s);
 }
 
 template <int W, int OP>
@@ -120,14 +140,19 @@ static int launch_blas(void* d_c, const void* d_a, const void* d_b, size_t n, co
   // at most 8 blocks per CU in flight; beyond that the grid-stride loop iterates
   u64 grid = chunks < 2048 ? chunks : 2048;
   if (grid == 0) grid = 1;
-  if (OP == OP_MUL && M.shift != 0)
-    hipLaunchKernelGGL((blas_kernel<W, OP, VEC, true>), dim3((unsigned)grid), dim3(THREADS), 0, stream,
-                       reinterpret_cast<Res<W>*>(d_c), reinterpret_cast<const Res<W>*>(d_a),
-                       reinterpret_cast<const Res<W>*>(d_b), (u64)n, M, s);
-  else
-    hipLaunchKernelGGL((blas_kernel<W, OP, VEC, false>), dim3((unsigned)grid), dim3(THREADS), 0, stream,
-                       reinterpret_cast<Res<W>*>(d_c), reinterpret_cast<const Res<W>*>(d_a),
-                       reinterpret_cast<const Res<W>*>(d_b), (u64)n, M, s);
+  const unsigned g = (unsigned)grid;
+  if constexpr (OP == OP_MUL) {
+    const bool kara = g_kara[width_slot(W / 2)].load(std::memory_order_relaxed) != 0;
+    if (M.shift != 0) {
+      if (kara) launch_blas_kernel<W, OP, true, true>(g, stream, d_c, d_a, d_b, n, M, s);
+      else launch_blas_kernel<W, OP, true, false>(g, stream, d_c, d_a, d_b, n, M, s);
+    } else {
+      if (kara) launch_blas_kernel<W, OP, false, true>(g, stream, d_c, d_a, d_b, n, M, s);
+      else launch_blas_kernel<W, OP, false, false>(g, stream, d_c, d_a, d_b, n, M, s);
+    }
+  } else {
+    launch_blas_kernel<W, OP, false, false>(g, stream, d_c, d_a, d_b, n, M, s);
+  }
   return hipGetLastError() == hipSuccess ? MW_OK : MW_EDEVICE;
 }
 
@@ -253,6 +278,20 @@ extern "C" int vec_axpymod(void* d_y, const uint64_t* alpha, const void* d_x, si
                            uint32_t limbs, void* stream) {
   // y <- alpha*x + y: the kernel reads (a = x, b = y) and writes c = y
   return blas_dispatch<OP_AXPY>(d_y, d_x, d_y, n, q, limbs, alpha, stream);
+}
+
+extern "C" int vec_mulmod_set_product(uint32_t limbs, uint32_t karatsuba) {
+  const int k = width_slot(limbs);
+  if (k < 0 || karatsuba > 1) return MW_EINVAL;
+  g_kara[k].store(karatsuba, std::memory_order_relaxed);
+  return MW_OK;
+}
+
+extern "C" int vec_mulmod_get_product(uint32_t limbs, uint32_t* karatsuba) {
+  const int k = width_slot(limbs);
+  if (k < 0 || !karatsuba) return MW_EINVAL;
+  *karatsuba = g_kara[k].load(std::memory_order_relaxed);
+  return MW_OK;
 }
 
 extern "C" int mw_copy(void* dst, const void* src, size_t bytes, void* stream) {

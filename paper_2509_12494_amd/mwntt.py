@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
         "mw_canonical_root": (ctypes.c_int, [u64p, u32, u32, u64p]),
         "mw_shoup_companion": (ctypes.c_int, [u64p, u64p, u32, u64p]),
         "mw_barrett_mu": (ctypes.c_int, [u64p, u32, u64p]),
+        "vec_mulmod_set_product": (ctypes.c_int, [u32, u32]),
+        "vec_mulmod_get_product": (ctypes.c_int, [u32, ctypes.POINTER(u32)]),
         "mw_set_validate": (ctypes.c_int, [ctypes.c_int]),
         "mw_get_validate": (ctypes.c_int, []),
         "mw_check": (ctypes.c_int, [vp]),
@@ -477,6 +479,17 @@ def copy_to_tensor(ptr: int, like, stream=None):
     nbytes = out.numel() * out.element_size()
     _check(lib().mw_copy(out.data_ptr(), ptr, nbytes, _stream(stream)), "mw_copy")
     return out
+
+
+def set_mulmod_product(limbs: int, karatsuba: bool) -> None:
+    """vec_mulmod's full product for one width: Karatsuba (Eq. mulk) or schoolbook."""
+    _check(lib().vec_mulmod_set_product(limbs, 1 if karatsuba else 0), "vec_mulmod_set_product")
+
+
+def get_mulmod_product(limbs: int) -> bool:
+    k = ctypes.c_uint32()
+    _check(lib().vec_mulmod_get_product(limbs, ctypes.byref(k)), "vec_mulmod_get_product")
+    return bool(k.value)
 
 
 # ---------------------------------------------------------------------------

@@ -10,6 +10,8 @@
 // Reads one case per line from stdin and writes the result words in hex:
 //   shoup  W q x w ws        -> T        (x < 2^(32W), w < q)
 //   barrett W q a b          -> r
+//   barrettk W q a b         -> r        (Barrett with the Karatsuba product)
+//   kara W q a b             -> a*b      (2W words, any a, b < 2^(32W); q unused)
 //   addmod / submod W q a b  -> r
 //   ct     W q X Y w ws      -> X' Y'    (Cooley-Tukey, inputs in [0, 16q))
 //   gs     W q X Y w ws      -> X' Y'    (Gentleman-Sande, inputs in [0, 8q))
@@ -95,6 +97,23 @@ bool run(const std::string& op, std::istringstream& in, std::string& out) {
     u32 w[W], ws[W];
     if (!parse<W>(a1, x.v) || !parse<W>(a2, w) || !parse<W>(a3, ws)) return false;
     out = hex<W>(shoup_mul(x, w, ws, M).v);
+  } else if (op == "kara") {
+    in >> a1 >> a2;
+    u32 a[W], b[W], r[2 * W];
+    if (!parse<W>(a1, a) || !parse<W>(a2, b)) return false;
+    mul_full_kara<W>(a, b, r);
+    u32 hi[W], lo[W];
+    for (int i = 0; i < W; ++i) {
+      lo[i] = r[i];
+      hi[i] = r[W + i];
+    }
+    out = hex<W>(hi) + hex<W>(lo);
+  } else if (op == "barrettk") {
+    in >> a1 >> a2;
+    Res<W> a, b;
+    if (!parse<W>(a1, a.v) || !parse<W>(a2, b.v)) return false;
+    const Res<W> r = M.shift ? barrett_mul_t<W, true, true>(a, b, M) : barrett_mul_t<W, false, true>(a, b, M);
+    out = hex<W>(r.v);
   } else if (op == "barrett" || op == "addmod" || op == "submod") {
     in >> a1 >> a2;
     Res<W> a, b;

@@ -203,3 +203,35 @@ def test_every_width_edges_and_ragged(bits):
             mwntt.vec_axpymod(y, alpha, a, q, limbs)
             torch.cuda.synchronize()
             assert host_ints(y, limbs) == oracle.modarith.vec_axpymod(alpha, ai, bi, q), (alpha, n)
+
+
+@pytest.mark.parametrize("bits", [14, 33, 60, 61, 97, 124, 125, 200, 252])
+def test_karatsuba_product_matches_oracle(bits):
+    """vec_mulmod with the full product of its Barrett reduction formed by one
+    level of Karatsuba (Eq. mulk) instead of the schoolbook columns: every
+    pair of edge residues, a ragged vector and the 2^16 length, whole outputs
+    against the oracle, for both products; the width's default is restored."""
+    require_gpu()
+    import torch
+    q = _any_modulus(bits)
+    limbs = W.limbs_for_bits(bits)
+    ev = sorted(set(v % q for v in edge_values(q)))
+    pairs = list(itertools.product(ev, ev))
+    cases = [(W.from_ints([x for x, _ in pairs], limbs), W.from_ints([y for _, y in pairs], limbs))]
+    for n in (4099, 1 << 16):
+        cases.append((W.uniform_residues(W.rng(bits + n), q, n, limbs),
+                      W.uniform_residues(W.rng(bits + n + 1), q, n, limbs)))
+    default = mwntt.get_mulmod_product(limbs)
+    try:
+        for kara in (True, False):
+            mwntt.set_mulmod_product(limbs, kara)
+            assert mwntt.get_mulmod_product(limbs) is kara
+            for A, B in cases:
+                announce("karatsuba" if kara else "schoolbook", len(A), bits)
+                a, b = dev(A), dev(B)
+                c = torch.empty_like(a)
+                mwntt.vec_mulmod(c, a, b, q, limbs)
+                torch.cuda.synchronize()
+                assert host_ints(c, limbs) == _oracle("vec_mulmod", W.to_ints(A), W.to_ints(B), q), (kara, len(A))
+    finally:
+        mwntt.set_mulmod_product(limbs, default)

@@ -8,7 +8,8 @@ Eq. barrett; Eq. muls for the word products):
 * Shoup x*w mod q up to a multiple of q, in [0, 6q) for one and two words and
   [0, 3q) for four words, for every x < 2^(32W);
 * Barrett a*b mod q canonical for a, b < q (the scaled modulus below the top of
-  a class);
+  a class), with the schoolbook and with the Karatsuba product (Eq. mulk);
+* the Karatsuba full product exact for any operands below 2^(32W);
 * canonical modular add and sub;
 * the butterflies' congruences and lazy ranges: forward inputs [0, 16q) ->
   X' in [0, 14q), Y' in (2q, 16q); inverse inputs [0, 8q) -> X' in [0, 8q),
@@ -101,6 +102,7 @@ def test_device_arithmetic_on_host(emulator, words):
         for a in res[::2]:
             for b in res[1::3]:
                 add(("barrett", a, b), lambda r, a=a, b=b: r[0] == a * b % q)
+                add(("barrettk", a, b), lambda r, a=a, b=b: r[0] == a * b % q)
                 add(("addmod", a, b), lambda r, a=a, b=b: r[0] == (a + b) % q)
                 add(("submod", a, b), lambda r, a=a, b=b: r[0] == (a - b) % q)
         for w in ws[:5]:
@@ -120,6 +122,8 @@ def test_device_arithmetic_on_host(emulator, words):
                 lambda r, X=X, Y=Y: r[0] == (X + Y) * ninv % q and r[1] == (X - Y) * m % q)
         for x in lazy16:
             add(("canon", x), lambda r, x=x: r[0] == x % q)
+        for a, b in zip(anyx, reversed(anyx)):
+            add(("kara", a, b), lambda r, a=a, b=b: r[0] == a * b)
         got = _run(emulator, lines)
         bad = [(ln, g) for ln, g, c in zip(lines, got, checks) if not c(g)]
         assert not bad, f"{len(bad)} of {len(lines)} cases fail at {q.bit_length()} bits, first: {bad[0]}"
