@@ -132,6 +132,19 @@ typedef struct ntt_plan_s* ntt_plan_t;
 #define NTT_BITREV_OUT 0x1u
 /* ntt_inverse reads its input in bit-reversed order.                        */
 #define NTT_BITREV_IN 0x2u
+/* Arithmetic variants of the butterfly, for the GPU analog of the paper's MQX
+ * ablation (Evaluation, sensitivity to the MQX components; Table tab:mqx):
+ * NTT_ARITH_MULHI forms every 32x32 product from v_mul_lo_u32 and
+ * v_mul_hi_u32 instead of the widening multiply-add v_mad_u64_u32;
+ * NTT_ARITH_CMPCARRY recovers every carry and borrow by a compare and a select
+ * instead of the hardware carry-out / carry-in; both together remove both.
+ * Results are identical to the native arithmetic.  Only for two-word moduli
+ * and N = 2^16 (MW_EINVAL otherwise); such a plan runs one fixed two-pass
+ * shape (N1 = N2 = 2^8), rejects ntt_plan_set_split / set_tiles, and is
+ * accepted by the plain entry points only (not by the batched executor or
+ * the serving runtime). */
+#define NTT_ARITH_MULHI 0x10u
+#define NTT_ARITH_CMPCARRY 0x20u
 
 /* Creates a plan on the current HIP device: builds the twiddle tables
  * (psi^bitrev(i) and psi^-bitrev(i) with their Shoup companions) on the host

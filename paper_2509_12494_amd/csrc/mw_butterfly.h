@@ -59,4 +59,26 @@ __device__ __forceinline__ Res<W> canon16(const Res<W>& x, const Modulus<W>& M) 
   return csub(csub(csub(csub(x, M.q8), M.q4), M.q2), M.q);
 }
 
+// The butterflies as a policy type for the tile engines (the arithmetic
+// variants of mw_ablation.h provide the same four functions).
+struct NativeBfly {
+  template <int W>
+  static __device__ __forceinline__ void ct(Res<W>& X, Res<W>& Y, const Tw<W>& t, const Modulus<W>& M) {
+    ct_bfly(X, Y, t, M);
+  }
+  template <int W>
+  static __device__ __forceinline__ void gs(Res<W>& X, Res<W>& Y, const Tw<W>& t, const Modulus<W>& M) {
+    gs_bfly(X, Y, t, M);
+  }
+  template <int W>
+  static __device__ __forceinline__ void gs_last(Res<W>& X, Res<W>& Y, const Tw<W>& ninv, const Tw<W>& ninv_w1,
+                                                 const Modulus<W>& M) {
+    gs_bfly_last(X, Y, ninv, ninv_w1, M);
+  }
+  template <int W>
+  static __device__ __forceinline__ Res<W> canon(const Res<W>& x, const Modulus<W>& M) {
+    return canon16(x, M);
+  }
+};
+
 }  // namespace mw

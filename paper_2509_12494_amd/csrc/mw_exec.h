@@ -14,7 +14,7 @@ namespace mw {
 
 // Accessors into an ntt_plan_s (defined in mw_ntt.hip).
 struct PlanView {
-  uint32_t log2n, limbs, flags;
+  uint32_t log2n, limbs, flags, variant;
   const uint64_t* q;
   const void* tw_fwd;
   const void* tw_inv;

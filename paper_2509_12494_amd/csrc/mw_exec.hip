@@ -284,6 +284,7 @@ int exec_build(const ntt_job* jobs, uint32_t count, ExecPlan& out) {
     c4 = {};
     c2 = {};
     if (!plan_view(jb.plan, v, c8, c4, c2)) return MW_EINVAL;
+    if (v.variant) return MW_EINVAL;    // arithmetic-variant plans run the plain entry points only
     if (v.log2n < 6) return MW_ESIZE;   // two-pass tiles need N1, N2 >= 8
     if (jb.op == NTT_JOB_POLYMUL && check_modulus(v.q, v.limbs) != MW_OK) return MW_EMODULUS;
     JobDesc& d = out.jobs[i];

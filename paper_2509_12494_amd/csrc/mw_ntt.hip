@@ -21,6 +21,9 @@
 #include "mw_validate.h"
 
 namespace mw {
+// Arithmetic-variant tile kernels (mw_ntt_ablation.hip).
+hipError_t launch_ntt_variant(int variant, int dir, int mode, const NttParams<4>& p, u32 blocks, hipStream_t s);
+
 // Largest single-workgroup transform and points-per-lane exponent of a width
 // (limbs 64-bit words per residue; see max_full_log / max_logp).
 inline uint32_t max_full_for(uint32_t limbs) { return (uint32_t)max_full_log(2 * (int)limbs); }
@@ -54,6 +57,7 @@ struct ntt_plan_s {
   // every call.
   PlanConfig lat, thr;
   bool forced = false;
+  uint32_t variant = 0;       // arithmetic variant (NTT_ARITH_* flags), 0 native
   uint64_t q[4] = {0, 0, 0, 0};
   uint64_t psi[4] = {0, 0, 0, 0};
   int device = 0;
@@ -173,6 +177,9 @@ hipError_t launch_pass(int dir, int mode, const ntt_plan_s* P, const PlanConfig&
                        hipStream_t s) {
   const u32 logl = mode == MODE_FULL ? P->log2n : (mode == MODE_COL ? C.log_n1 : P->log2n - C.log_n1);
   p.lines = C.cfg[mode].lines;
+  if constexpr (W == 4) {
+    if (P->variant) return launch_ntt_variant((int)P->variant, dir, mode, p, blocks, s);
+  }
   return dir == DIR_FWD ? launch_ntt<W, DIR_FWD>(mode, logl, C.cfg[mode].logp, p, blocks, s)
                         : launch_ntt<W, DIR_INV>(mode, logl, C.cfg[mode].logp, p, blocks, s);
 }
@@ -376,6 +383,7 @@ bool plan_view(const ntt_plan_s* P, PlanView& v, ModConst<8>& c8, ModConst<4>& c
   v.log2n = P->log2n;
   v.limbs = P->limbs;
   v.flags = P->flags;
+  v.variant = P->variant;
   v.q = P->q;
   v.tw_fwd = P->d_tw_fwd;
   v.tw_inv = P->d_tw_inv;
@@ -452,7 +460,9 @@ extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint
                         const uint64_t* psi, uint32_t flags) {
   if (!out) return MW_EINVAL;
   *out = nullptr;
-  if (flags & ~(NTT_BITREV_OUT | NTT_BITREV_IN)) return MW_EINVAL;
+  if (flags & ~(NTT_BITREV_OUT | NTT_BITREV_IN | NTT_ARITH_MULHI | NTT_ARITH_CMPCARRY)) return MW_EINVAL;
+  const uint32_t variant = (flags & NTT_ARITH_MULHI ? 1u : 0u) | (flags & NTT_ARITH_CMPCARRY ? 2u : 0u);
+  if (variant && (limbs != 2 || log2n != 16)) return MW_EINVAL;
   if (log2n < 1 || log2n > 17) return MW_ESIZE;
   int st = check_modulus(q, limbs);
   if (st != MW_OK) return st;
@@ -474,6 +484,16 @@ extern "C" int ntt_plan(ntt_plan_t* out, uint32_t log2n, const uint64_t* q, uint
     return st;
   }
   initial_configs(P);
+  if (variant) {
+    // the variant kernels' one shape, for every call
+    P->variant = variant;
+    P->forced = true;
+    PlanConfig C;
+    C.log_n1 = 8;
+    C.cfg[MODE_COL] = {2, 4};
+    C.cfg[MODE_ROW] = {2, 4};
+    P->lat = P->thr = C;
+  }
   if (P->lat.log_n1 || P->thr.log_n1) {
     st = ensure_scratch(P);
     if (st != MW_OK) {
@@ -540,7 +560,7 @@ extern "C" int ntt_forward_pass(ntt_plan_t plan, uint32_t pass, void* d_out, con
 }
 
 extern "C" int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1) {
-  if (!plan) return MW_EINVAL;
+  if (!plan || plan->variant) return MW_EINVAL;
   const uint32_t max_full = max_full_for(plan->limbs);
   if (log_n1 == 0) {
     if (plan->log2n > max_full) return MW_ESIZE;
@@ -561,7 +581,7 @@ extern "C" int ntt_plan_set_split(ntt_plan_t plan, uint32_t log_n1) {
 static PlanConfig& visible_config(ntt_plan_t plan) { return plan->forced ? plan->lat : plan->thr; }
 
 extern "C" int ntt_plan_set_tiles(ntt_plan_t plan, uint32_t pass, uint32_t log_p, uint32_t lines) {
-  if (!plan || pass > 2) return MW_EINVAL;
+  if (!plan || pass > 2 || plan->variant) return MW_EINVAL;
   PlanConfig C = visible_config(plan);
   const uint32_t logn = plan->log2n;
   uint32_t logl, max_lines;

@@ -172,7 +172,7 @@ __device__ __forceinline__ void round_sync(bool last) {
 // lane's point u sits at line index base_j | (u << L0), L0 = LOGL - s0 - LOGP;
 // the stages of the round pair the top np bits of u.  Rounds and stages are
 // compile-time recursions so every register index is a constant.
-template <int W, int LOGL, int LOGP, int DIR, int RIDX>
+template <int W, int LOGL, int LOGP, int DIR, int RIDX, class BF = NativeBfly>
 struct Round {
   using S = LineShape<LOGL, LOGP>;
   static constexpr int P = S::P;
@@ -195,15 +195,15 @@ struct Round {
 #pragma unroll
         for (int lo = 0; lo < (1 << ib); ++lo) {
           const int u = (gi << (ib + 1)) | lo;
-          gs_bfly_last(x[u], x[u | (1 << ib)], p.ninv, p.ninv_w1, p.M);
+          BF::gs_last(x[u], x[u | (1 << ib)], p.ninv, p.ninv_w1, p.M);
         }
       } else {
         const Tw<W> t = load_tw(tw, (base << s) + g);
 #pragma unroll
         for (int lo = 0; lo < (1 << ib); ++lo) {
           const int u = (gi << (ib + 1)) | lo;
-          if (DIR == DIR_FWD) ct_bfly(x[u], x[u | (1 << ib)], t, p.M);
-          else gs_bfly(x[u], x[u | (1 << ib)], t, p.M);
+          if (DIR == DIR_FWD) BF::ct(x[u], x[u | (1 << ib)], t, p.M);
+          else BF::gs(x[u], x[u | (1 << ib)], t, p.M);
         }
       }
     }
@@ -219,7 +219,7 @@ struct Round {
     stage<0>(x, base_j, base, tw, p, last_inv);
     if (canon) {
 #pragma unroll
-      for (int u = 0; u < P; ++u) x[u] = canon16(x[u], p.M);
+      for (int u = 0; u < P; ++u) x[u] = BF::canon(x[u], p.M);
     }
 #pragma unroll
     for (int u = 0; u < P; ++u) line[pad_idx<LOGL, LOGP>(base_j | ((u32)u << L0))] = x[u];
@@ -231,14 +231,15 @@ struct Round {
 // tid: lane index within the line; base: twiddle base (1, or N1 + b for rows);
 // last_inv: the line contains the final inverse stage (fold N^-1);
 // final_fwd: canonicalize after the last forward stage.
-template <int W, int LOGL, int LOGP, int DIR, int RR = 0>
+template <int W, int LOGL, int LOGP, int DIR, int RR = 0, class BF = NativeBfly>
 __device__ __forceinline__ void line_stages(Res<W>* line, u32 tid, u32 base, const Tw<W>* __restrict__ tw,
                                             const NttParams<W>& p, bool last_inv, bool final_fwd) {
   using S = LineShape<LOGL, LOGP>;
   constexpr int R = (DIR == DIR_FWD) ? RR : (S::R - 1 - RR);
-  Round<W, LOGL, LOGP, DIR, R>::run(line, tid, base, tw, p, last_inv,
+  Round<W, LOGL, LOGP, DIR, R, BF>::run(line, tid, base, tw, p, last_inv,
                                     DIR == DIR_FWD && final_fwd && RR == S::R - 1, RR == S::R - 1);
-  if constexpr (RR + 1 < S::R) line_stages<W, LOGL, LOGP, DIR, RR + 1>(line, tid, base, tw, p, last_inv, final_fwd);
+  if constexpr (RR + 1 < S::R)
+    line_stages<W, LOGL, LOGP, DIR, RR + 1, BF>(line, tid, base, tw, p, last_inv, final_fwd);
 }
 
 // Number of tiles one launch of a pass covers.
@@ -253,7 +254,7 @@ __host__ __device__ inline u32 tiles_per_poly(u32 log_n, u32 log_n1, u32 lines) 
 // All threads of the workgroup take part (lines * L/P threads); `lds` holds
 // lines * NPAD residues.  For MODE_FULL, `tile` indexes groups of `lines`
 // transforms; otherwise it indexes (poly, tile-within-poly).
-template <int W, int LOGL, int LOGP, int DIR, int MODE>
+template <int W, int LOGL, int LOGP, int DIR, int MODE, class BF = NativeBfly>
 __device__ __forceinline__ void ntt_tile(const NttParams<W>& p, Res<W>* lds, u32 tile) {
   using S = LineShape<LOGL, LOGP>;
   constexpr int L = S::L;
@@ -328,7 +329,7 @@ __device__ __forceinline__ void ntt_tile(const NttParams<W>& p, Res<W>* lds, u32
   if (MODE == MODE_ROW) base = (1u << log_n1) + line_id * ((1u << log_n1) >> log_lines) + b_lo;
   const bool last_inv = (DIR == DIR_INV) && (MODE != MODE_ROW);
   const bool final_fwd = (DIR == DIR_FWD) && (MODE != MODE_COL);
-  line_stages<W, LOGL, LOGP, DIR>(lds + line_id * S::NPAD, lane, base, p.tw, p, last_inv, final_fwd);
+  line_stages<W, LOGL, LOGP, DIR, 0, BF>(lds + line_id * S::NPAD, lane, base, p.tw, p, last_inv, final_fwd);
 
   // ---- LDS -> device memory ----
   if (MODE == MODE_FULL) {

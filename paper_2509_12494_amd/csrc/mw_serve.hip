@@ -367,7 +367,7 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
     ModConst<8> c8;
     ModConst<4> c4;
     ModConst<2> c2;
-    if (!plan_view(r.plan, v, c8, c4, c2)) return MW_EINVAL;
+    if (!plan_view(r.plan, v, c8, c4, c2) || v.variant) return MW_EINVAL;
     if (v.log2n < 6) return MW_ESIZE;
     if (op == MW_REQ_POLYMUL) {
       if (!r.in2) return MW_EINVAL;

@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(HERE, "libmwntt.so")
 MW_OK = 0
 NTT_BITREV_OUT = 0x1
 NTT_BITREV_IN = 0x2
+NTT_ARITH_MULHI = 0x10
+NTT_ARITH_CMPCARRY = 0x20
 
 NTT_JOB_FORWARD = 0
 NTT_JOB_INVERSE = 1
