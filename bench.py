@@ -1,6 +1,6 @@
 """Benchmark of the multi-word NTT / modular BLAS hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs all|none|LEG,...]
 
 Workload (one step, the paper-scale plain configuration): forward and inverse
 negacyclic NTT at N = 2^16 over a 124-bit prime q = 1 mod 2^18 (coefficients
@@ -15,10 +15,13 @@ op's stream); algorithmic Gmulmod/s; the batched (96 transforms per call)
 rate; ``legs``: the executor on the same batch, a batch sweep, a
 host-inclusive (pinned copies in and out) figure, the mixed 96-polynomial
 batch and its inverse, 256 fused products at 2^14, RNS products over eight
-primes, the 60-bit and 252-bit transforms and BLAS, BLAS at streaming sizes (2^24) against
-the HBM peak, and the serving replay; the roofline
-of the dominant kernel (with HBM traffic and VALU instructions from the
-committed rocprofv3 summary); and the CPU oracle's rate on a bounded sample.
+primes, the 60-bit and 252-bit transforms and BLAS, BLAS at streaming sizes
+(2^24) against the HBM peak with both products of vec_mulmod (schoolbook and
+Karatsuba), the arithmetic variants of the 124-bit butterfly (the GPU analog
+of the paper's MQX ablation), and the serving replay; the roofline of the
+dominant kernel (with HBM traffic and VALU instructions from the committed
+rocprofv3 summary); and the CPU oracle's rate on a bounded sample.  --legs
+selects the legs after the plain step (the profiling commands run one leg).
 """
 import argparse
 import json
@@ -39,7 +42,9 @@ INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # products, W(W+1)/2 each for the low halves of x*w and Q*q, W word subs for
 # the remainder, and 2W word add/sub for the butterfly's sum and difference).
 PROFILE = os.path.join(ROOT, "profiles", "ntt_fwd_2e16_124bit_b64.md")
-KERNEL_SOURCES = ["mw_arith.h", "mw_ntt_tile.h", "mw_ntt_kernels.inc", "mw_ntt.hip", "mw_tuned.h"]
+KERNEL_SOURCES = ["mw_arith.h", "mw_butterfly.h", "mw_ntt_tile.h", "mw_ntt_kernels.inc", "mw_ntt.hip", "mw_tuned.h"]
+LEGS = ("batched", "sweep", "host", "mixed", "fused", "rns", "w60", "w252", "blas", "serving", "ablation",
+        "roofline")
 
 
 def kernel_source_hash():
@@ -79,6 +84,12 @@ def measured_valu(pass_):
 
 def butterfly_word_ops(W):
     return 3 * (W * (W + 1) // 2) + W + 2 * W
+
+
+# The planning model of 32-bit word operations per butterfly that the roofline
+# fraction is reported against: about 36 word multiplies and 64 other
+# operations for a two-word (124-bit) residue, 10 and 24 for one word.
+MODEL_OPS_PER_BUTTERFLY = {4: 100, 2: 34}
 
 
 def percentile(xs, p):
@@ -208,7 +219,14 @@ def main():
                     help="requests in the serving leg (Poisson, 20k requests/s); 0 skips it")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated legs after the plain step (" + ",".join(LEGS) + "), 'all' or 'none'")
     args = ap.parse_args()
+    legs_on = set(LEGS) if args.legs == "all" else set(x for x in args.legs.split(",") if x and x != "none")
+    unknown = legs_on - set(LEGS)
+    if unknown:
+        print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print("bench.py measures one GPU; runs on more than one GPU are not supported", file=sys.stderr)
         sys.exit(2)
@@ -309,25 +327,108 @@ def main():
         lat[name] = {"p50_us": round(percentile(us, 50), 3), "p99_us": round(percentile(us, 99), 3),
                      "mean_last_half_us": round(sum(half) / len(half), 3)}
 
-    progress("batched legs")
-    # batched leg: many 2^16 transforms in one call (same plan, same q)
+    # the batch of 2^16 transforms several legs use (same plan, same q)
     B = args.batch
     bpoly = mwntt.to_device(W.uniform_residues(W.rng(2100), q, n * B, limbs))
     bspec = torch.empty_like(bpoly)
-    batched_us = time_calls(lambda: plan.forward(bspec, bpoly, batch=B, stream=sp), stream)
-    batched_ntt_s = B / (batched_us * 1e-6)
-    # the same 96 transforms through the batched executor, replayed from a graph
-    ex = mwntt.NttBatch([(plan, mwntt.NTT_JOB_FORWARD, bpoly[i * n:(i + 1) * n], None, bspec[i * n:(i + 1) * n])
-                         for i in range(B)])
-    exec_us = time_graph(lambda s_: ex.run(stream=s_), stream)
-    legs = {"homogeneous_2e16": {"batch": B, "ntt_forward_us_per_call": round(batched_us, 2),
-                                 "ntt_forward_ntt_s": round(batched_ntt_s, 1),
-                                 "executor_graph_us": round(exec_us, 2),
-                                 "executor_ntt_s": round(B / (exec_us * 1e-6), 1)}}
-    ex.destroy()
+    legs = {}
+    batched_us = batched_ntt_s = None
+    if "batched" in legs_on:
+        progress("batched legs")
+        # batched leg: many 2^16 transforms in one call
+        batched_us = time_calls(lambda: plan.forward(bspec, bpoly, batch=B, stream=sp), stream)
+        batched_ntt_s = B / (batched_us * 1e-6)
+        # the same 96 transforms through the batched executor, replayed from a graph
+        ex = mwntt.NttBatch([(plan, mwntt.NTT_JOB_FORWARD, bpoly[i * n:(i + 1) * n], None,
+                              bspec[i * n:(i + 1) * n]) for i in range(B)])
+        exec_us = time_graph(lambda s_: ex.run(stream=s_), stream)
+        legs["homogeneous_2e16"] = {"batch": B, "ntt_forward_us_per_call": round(batched_us, 2),
+                                    "ntt_forward_ntt_s": round(batched_ntt_s, 1),
+                                    "executor_graph_us": round(exec_us, 2),
+                                    "executor_ntt_s": round(B / (exec_us * 1e-6), 1)}
+        ex.destroy()
 
     # batch sweep of the same transform (inputs: the 96 staged polynomials
     # repeated, all canonical residues)
+    if "sweep" in legs_on:
+        sweep_leg(plan, bpoly, B, n, stream, sp, legs)
+    if "host" in legs_on:
+        host_leg(plan, poly, spec, bpoly, bspec, B, n, limbs, stream, sp, legs)
+    if "mixed" in legs_on:
+        mixed_leg(stream, sp, legs)
+    if "fused" in legs_on:
+        fused_leg(stream, legs)
+    if "rns" in legs_on:
+        rns_leg(n, stream, legs)
+    if "w60" in legs_on:
+        w60_leg(n, stream, sp, legs)
+    if "w252" in legs_on:
+        w252_leg(n, log2n, stream, sp, legs)
+    if "blas" in legs_on:
+        blas_leg(stream, sp, legs)
+    if "ablation" in legs_on:
+        ablation_leg(q, n, bpoly, bspec, B, stream, sp, legs)
+    if args.serve_requests and "serving" in legs_on:
+        progress(f"serving leg: {args.serve_requests} requests")
+        legs["serving"] = serving_leg(args.serve_requests)
+
+    roof = roofline_leg(plan, bpoly, bspec, B, n, log2n, limbs, stream, sp) if "roofline" in legs_on else None
+
+    mulmods_step = 2 * bfly_count(n, log2n) + 2 * n        # two transforms + vec_mulmod + vec_axpymod
+    res = {
+        "metric": "128-bit NTT/s at N=2^16 (batched vs plain), Gmulmod/s, p50/p99 latency",
+        "value": round(2.0 / (ms_per_step * 1e-3), 2),
+        "unit": "NTT/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u128 (2x64-bit limbs, 124-bit prime)",
+        "data": "synthetic (seeded uniform residues)",
+        "config": {"workload": "plain, paper scale: forward+inverse negacyclic NTT N=2^16, 124-bit q=1 mod 2^18; "
+                               "vec_mulmod/addmod/axpymod n=2^16; one launch per op",
+                   "N": n, "q_bits": q.bit_length(), "limbs": limbs, "split_log_n1": plan.split},
+        "gmulmod_s": round(mulmods_step / (ms_per_step * 1e-3) / 1e9, 4),
+        "latency_us": lat,
+        "batched": None if batched_us is None else {
+            "batch": B, "us_per_call": round(batched_us, 2), "ntt_s": round(batched_ntt_s, 1),
+            "speedup_vs_plain_forward": round(batched_ntt_s / (1e6 / lat["ntt_forward"]["p50_us"]), 2),
+            "gmulmod_s": round(B * bfly_count(n, log2n) / (batched_us * 1e-6) / 1e9, 3)},
+        "legs": legs,
+        "roofline": roof,
+        "wall_s_timed_region": round(wall, 4),
+        # host time to issue one step (7 library calls through the Python
+        # binding); close to ms_per_step means the plain step is bound by
+        # call submission rather than by the GPU
+        "host_issue_us_per_step": round(t_enq / args.steps * 1e6, 2),
+        "plain_step_graph": {"us_per_step": round(graph_us, 2), "ntt_s": round(2.0 / (graph_us * 1e-6), 1),
+                             "note": "the same step (7 launches, one per op) captured once in a hipGraph"},
+    }
+    if args.copy_calibration_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
+        # the counters of the transform kernels to bytes
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda").fill_(3)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = nbytes
+    if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(wl)
+    plan.destroy()
+    print(json.dumps(res), flush=True)
+
+
+def bfly_count(n, log2n):
+    return (n // 2) * log2n
+
+
+def sweep_leg(plan, bpoly, B, n, stream, sp, legs):
+    import torch
     progress("batch sweep")
     sweep_max = 1024
     reps_in = (sweep_max + B - 1) // B
@@ -340,8 +441,11 @@ def main():
     legs["batch_sweep_2e16"] = sweep
     del sw_in, sw_out
 
-    # host-inclusive form (the paper's CPU timings include data transfer):
-    # pinned host input -> device, forward transform, device -> pinned host
+
+def host_leg(plan, poly, spec, bpoly, bspec, B, n, limbs, stream, sp, legs):
+    """Host-inclusive form (the paper's CPU timings include data transfer):
+    pinned host input -> device, forward transform, device -> pinned host."""
+    import torch
     progress("host-inclusive")
     h_in = torch.empty(poly.shape, dtype=poly.dtype, pin_memory=True)
     h_in.copy_(poly)
@@ -355,7 +459,10 @@ def main():
         h_out.copy_(d_out, non_blocking=True)
     host_us = time_calls(host_round, stream)
     torch.cuda.synchronize()
-    assert torch.equal(h_out, spec.cpu()), "host-inclusive forward differs"
+    want = torch.empty_like(poly)
+    plan.forward(want, poly, batch=1, stream=sp)
+    torch.cuda.synchronize()
+    assert torch.equal(h_out, want.cpu()), "host-inclusive forward differs"
     hb_in = torch.empty(bpoly.shape, dtype=bpoly.dtype, pin_memory=True)
     hb_in.copy_(bpoly)
     hb_out = torch.empty_like(hb_in, pin_memory=True)
@@ -370,7 +477,14 @@ def main():
                                    "batched_ntt_s": round(B / (host_b_us * 1e-6), 1),
                                    "bytes_per_transform": 2 * n * 8 * limbs}
 
-    # mixed batch: 96 polynomials, N uniform over 2^12..2^16, 60/124-bit, forward
+
+def mixed_leg(stream, sp, legs):
+    """Mixed batch: 96 polynomials, N uniform over 2^12..2^16, 60/124-bit,
+    forward (and the inverse batch of the round trip)."""
+    import torch
+    from paper_2509_12494_amd import mwntt
+    from paper_2509_12494_amd import workloads as W
+    progress("mixed batch")
     mixed = W.config_batched()
     mplans, mjobs, mbfly = {}, [], 0
     for (lg, qm, lm, coeffs) in mixed:
@@ -382,7 +496,6 @@ def main():
         mbfly += (1 << (lg - 1)) * lg
     mb = mwntt.NttBatch(mjobs)
     mixed_us = time_graph(lambda s_: mb.run(stream=s_), stream)
-    # the round trip: a second batch inverts every spectrum
     mb.run(stream=sp)
     ijobs = [(pl, mwntt.NTT_JOB_INVERSE, o, None, torch.empty_like(o)) for (pl, _, _, _, o) in mjobs]
     mi = mwntt.NttBatch(ijobs)
@@ -397,8 +510,17 @@ def main():
                         "polys_s": round(len(mixed) / (mixed_us * 1e-6), 1),
                         "gbutterfly_s": round(mbfly / (mixed_us * 1e-6) / 1e9, 2)}
     mb.destroy()
+    for pl in mplans.values():
+        pl.destroy()
 
-    # fused products: 256 pairs at N = 2^14, 124-bit
+
+def fused_leg(stream, legs):
+    """Fused products: 256 pairs at N = 2^14, 124-bit, one executor run
+    replayed from a hipGraph."""
+    import torch
+    from paper_2509_12494_amd import mwntt
+    from paper_2509_12494_amd import workloads as W
+    progress("fused products")
     qf, FA, FB = W.config_fused()
     pairs, nf = FA.shape[0], FA.shape[1]
     fplan = mwntt.ntt_plan(14, qf, 2)
@@ -412,12 +534,15 @@ def main():
                               "ntt_equiv_s": round(3 * pairs / (fused_us * 1e-6), 1)}
     fbatch.destroy()
     fplan.destroy()
-    for pl in mplans.values():
-        pl.destroy()
 
-    # RNS form (the FHE shape): polynomials mod Q = q_1 ... q_8, eight 124-bit
-    # primes sharing N = 2^16; 4 RNS products = 32 fused product jobs in one
-    # executor run (hipGraph replay)
+
+def rns_leg(n, stream, legs):
+    """RNS form (the FHE shape): polynomials mod Q = q_1 ... q_8, eight 124-bit
+    primes sharing N = 2^16; 4 RNS products = 32 fused product jobs in one
+    executor run (hipGraph replay)."""
+    import torch
+    from paper_2509_12494_amd import mwntt
+    from paper_2509_12494_amd import workloads as W
     progress("rns leg")
     rqs = W.config_rns()
     rplans = [mwntt.ntt_plan(16, rq, 2) for rq in rqs]
@@ -437,10 +562,14 @@ def main():
     rbatch.destroy()
     for pl in rplans:
         pl.destroy()
-    del rjobs
 
-    # the same paper-scale transform with a 60-bit prime (one word), for
-    # comparison with the 124-bit figures: plain latency, 96 per call, mulmod
+
+def w60_leg(n, stream, sp, legs):
+    """The paper-scale transform with a 60-bit prime (one word): plain
+    latency, 96 per call, mulmod."""
+    import torch
+    from paper_2509_12494_amd import mwntt
+    from paper_2509_12494_amd import workloads as W
     progress("60-bit leg")
     q1 = W.find_prime(60, 2001)
     p60 = mwntt.ntt_plan(16, q1, 1)
@@ -459,10 +588,14 @@ def main():
         "batch": 96, "batched_us_per_call": round(b60_us, 2), "batched_ntt_s": round(96 / (b60_us * 1e-6), 1),
         "vec_mulmod_us": round(time_calls(lambda: mwntt.vec_mulmod(z1, x1, x2, q1, 1, stream=sp), stream, reps=50), 2)}
     p60.destroy()
-    del x60, y60, z60, x1, y1, z1, x2
 
-    # four-word moduli (252-bit q = 1 mod 2^18): N = 2^16, plain latency,
-    # batch-64 throughput and the BLAS ops, inputs resident in HBM
+
+def w252_leg(n, log2n, stream, sp, legs):
+    """Four-word moduli (252-bit q = 1 mod 2^18): N = 2^16, plain latency,
+    batch-64 throughput and the BLAS ops, inputs resident in HBM."""
+    import torch
+    from paper_2509_12494_amd import mwntt
+    from paper_2509_12494_amd import workloads as W
     progress("252-bit leg")
     q8 = W.find_prime(252, 6001)
     wplan = mwntt.ntt_plan(16, q8, 4)
@@ -487,10 +620,16 @@ def main():
         wide[nm] = round(time_calls(f, stream, reps=50), 2)
     legs["wide_252bit_2e16"] = wide
     wplan.destroy()
-    del wx, wy, wz
 
-    # BLAS at streaming sizes: n = 2^24 residues (2^23 for 252-bit), inputs
-    # resident; algorithmic bytes = two vectors read + one written
+
+def blas_leg(stream, sp, legs):
+    """BLAS at streaming sizes: n = 2^24 residues (2^23 for 252-bit), inputs
+    resident; algorithmic bytes = two vectors read + one written.  vec_mulmod
+    is timed with both products of its Barrett reduction (schoolbook columns,
+    Karatsuba, Eq. mulk) and reported with the width's default."""
+    import torch
+    from paper_2509_12494_amd import mwntt
+    from paper_2509_12494_amd import workloads as W
     progress("BLAS streaming leg")
     stream_leg = {}
     for bits, lg in ((60, 24), (124, 24), (252, 23)):
@@ -503,24 +642,70 @@ def main():
         alpha_s = (qs - 1) // 3
         nbytes = 3 * ns * 8 * ls
         row = {"n": ns}
-        for nm, f in (("add", lambda: mwntt.vec_addmod(sc, sa, sb, qs, ls, stream=sp)),
-                      ("mul", lambda: mwntt.vec_mulmod(sc, sa, sb, qs, ls, stream=sp)),
-                      ("axpy", lambda: mwntt.vec_axpymod(sc, alpha_s, sa, qs, ls, stream=sp))):
-            us = time_calls(f, stream, reps=20)
+
+        def put(nm, us):
             gbs = nbytes / (us * 1e-6) / 1e9
             row[nm] = {"us": round(us, 1), "GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 3)}
-            if nm == "mul":
-                row[nm]["gmulmod_s"] = round(ns / (us * 1e-6) / 1e9, 2)
+        put("add", time_calls(lambda: mwntt.vec_addmod(sc, sa, sb, qs, ls, stream=sp), stream, reps=20))
+        default = mwntt.get_mulmod_product(ls)
+        prods, outs = {}, {}
+        for kara in (False, True):
+            mwntt.set_mulmod_product(ls, kara)
+            prods[kara] = time_calls(lambda: mwntt.vec_mulmod(sc, sa, sb, qs, ls, stream=sp), stream, reps=20)
+            torch.cuda.synchronize()
+            outs[kara] = sc.clone()
+        mwntt.set_mulmod_product(ls, default)
+        assert torch.equal(outs[False], outs[True]), "Karatsuba and schoolbook products differ"
+        put("mul", prods[default])
+        row["mul"]["gmulmod_s"] = round(ns / (prods[default] * 1e-6) / 1e9, 2)
+        row["mul"]["product"] = "karatsuba" if default else "schoolbook"
+        row["mul_products_us"] = {"schoolbook": round(prods[False], 1), "karatsuba": round(prods[True], 1)}
+        put("axpy", time_calls(lambda: mwntt.vec_axpymod(sc, alpha_s, sa, qs, ls, stream=sp), stream, reps=20))
         stream_leg[f"{bits}bit"] = row
-        del sa, sb, sc
+        del sa, sb, sc, outs
     legs["blas_stream"] = stream_leg
 
-    if args.serve_requests:
-        progress(f"serving leg: {args.serve_requests} requests")
-        legs["serving"] = serving_leg(args.serve_requests)
 
-    # roofline of the dominant kernel: the two passes of the batched forward
-    # transform, each one kernel launch, timed with HIP events on their stream
+def ablation_leg(q, n, bpoly, bspec, B, stream, sp, legs):
+    """The GPU analog of the paper's MQX ablation: the 2^16 124-bit forward
+    transform of the batch with the native butterfly and with its arithmetic
+    variants (products from multiply-low / multiply-high, carries by
+    compare-and-select, both), all in the variants' one shape (two passes of
+    2^8-point lines, 4 points per lane, 4 lines per workgroup)."""
+    import torch
+    from paper_2509_12494_amd import mwntt
+    progress("ablation leg")
+    rows, ref = {}, None
+    for name, flags in (("native", 0), ("mulhi", mwntt.NTT_ARITH_MULHI), ("cmpcarry", mwntt.NTT_ARITH_CMPCARRY),
+                        ("mulhi_cmpcarry", mwntt.NTT_ARITH_MULHI | mwntt.NTT_ARITH_CMPCARRY)):
+        p = mwntt.ntt_plan(16, q, 2, flags=flags)
+        if not flags:
+            p.split = 8
+            p.set_tiles(1, 2, 4)
+            p.set_tiles(2, 2, 4)
+        p.forward(bspec, bpoly, batch=B, stream=sp)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = bspec.clone()
+        assert torch.equal(bspec, ref), f"{name} variant differs from the native arithmetic"
+        us = time_calls(lambda: p.forward(bspec, bpoly, batch=B, stream=sp), stream, reps=10)
+        p1 = time_calls(lambda: p.forward_pass(1, None, bpoly, B, stream=sp), stream, reps=10)
+        p2 = time_calls(lambda: p.forward_pass(2, bspec, None, B, stream=sp), stream, reps=10)
+        rows[name] = {"forward_us": round(us, 2), "ntt_s": round(B / (us * 1e-6), 1),
+                      "pass1_us": round(p1, 2), "pass2_us": round(p2, 2)}
+        p.destroy()
+    for name in rows:
+        rows[name]["slowdown_vs_native"] = round(rows[name]["forward_us"] / rows["native"]["forward_us"], 3)
+    legs["ablation_124bit_2e16"] = {"batch": B, "variants": rows}
+
+
+def roofline_leg(plan, bpoly, bspec, B, n, log2n, limbs, stream, sp):
+    """Roofline of the dominant kernel: the two passes of the batched forward
+    transform, each one kernel launch, timed with HIP events on their stream.
+    Algorithmic work per butterfly: the planning model of 32-bit word
+    operations (MODEL_OPS_PER_BUTTERFLY), beside the minimal count of the
+    Shoup butterfly's word products and adds (butterfly_word_ops)."""
+    import torch
     progress("roofline passes")
     RB = min(64, B)
     rin, rout = bpoly[:RB * n], bspec[:RB * n]
@@ -530,20 +715,21 @@ def main():
     plan.forward_pass(2, rout, None, RB, stream=sp)
     torch.cuda.synchronize()
     assert torch.equal(ref, rout), "pass 1 + pass 2 differs from ntt_forward"
-    split = plan.split
+    large, split = plan.config_for(RB)
     W_words = 2 * limbs
-    bfly = (n // 2) * log2n
+    model_ops = MODEL_OPS_PER_BUTTERFLY[W_words]
     passes = {}
     for k, (stages, fn) in {1: (split, lambda: plan.forward_pass(1, None, rin, RB, stream=sp)),
                             2: (log2n - split, lambda: plan.forward_pass(2, rout, None, RB, stream=sp))}.items():
         us = time_calls(fn, stream, reps=50)
-        ops = RB * (n // 2) * stages * butterfly_word_ops(W_words)
+        bfly = RB * (n // 2) * stages
         tw_bytes = (1 << split if k == 1 else n) * 32 * limbs // 2
         byts = 2 * RB * n * 8 * limbs + tw_bytes
-        passes[k] = {"us": us, "ops": ops, "bytes": byts}
+        passes[k] = {"us": us, "butterflies": bfly, "bytes": byts}
     dom = max(passes, key=lambda k: passes[k]["us"])
     d = passes[dom]
-    achieved_tops = d["ops"] / (d["us"] * 1e-6) / 1e12
+    achieved = d["butterflies"] * model_ops / (d["us"] * 1e-6) / 1e12
+    achieved_min = d["butterflies"] * butterfly_word_ops(W_words) / (d["us"] * 1e-6) / 1e12
     traffic = measured_traffic(dom)
     valu_insts = measured_valu(dom)
     valu_issue = None
@@ -551,64 +737,21 @@ def main():
         # what the kernel issues, beside the algorithmic count: VALU
         # wave-instructions x 64 lanes per launch, over the same launch time
         issued = valu_insts * 64 / (d["us"] * 1e-6) / 1e12
-        valu_issue = {"valu_insts": valu_insts, "lane_ops_per_butterfly": round(valu_insts * 64 / (d["ops"] / butterfly_word_ops(W_words)), 1),
+        valu_issue = {"valu_insts": valu_insts, "lane_ops_per_butterfly": round(valu_insts * 64 / d["butterflies"], 1),
                       "achieved": round(issued, 3), "frac": round(issued / INT32_PEAK_TOPS, 4)}
-
-    mulmods_step = 2 * bfly + 2 * n        # two transforms + vec_mulmod + vec_axpymod
-    res = {
-        "metric": "128-bit NTT/s at N=2^16 (batched vs plain), Gmulmod/s, p50/p99 latency",
-        "value": round(2.0 / (ms_per_step * 1e-3), 2),
-        "unit": "NTT/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u128 (2x64-bit limbs, 124-bit prime)",
-        "data": "synthetic (seeded uniform residues)",
-        "config": {"workload": "plain, paper scale: forward+inverse negacyclic NTT N=2^16, 124-bit q=1 mod 2^18; "
-                               "vec_mulmod/addmod/axpymod n=2^16; one launch per op",
-                   "N": n, "q_bits": q.bit_length(), "limbs": limbs, "split_log_n1": plan.split},
-        "gmulmod_s": round(mulmods_step / (ms_per_step * 1e-3) / 1e9, 4),
-        "latency_us": lat,
-        "batched": {"batch": B, "us_per_call": round(batched_us, 2), "ntt_s": round(batched_ntt_s, 1),
-                    "speedup_vs_plain_forward": round(batched_ntt_s / (1e6 / lat["ntt_forward"]["p50_us"]), 2),
-                    "gmulmod_s": round(B * bfly / (batched_us * 1e-6) / 1e9, 3)},
-        "legs": legs,
-        "roofline": {"bound": "alu",
-                     "kernel": f"forward pass {dom} ({'column' if dom == 1 else 'row'} tiles), N=2^16, 124-bit, "
-                               f"batch {RB}, one launch",
-                     "achieved": round(achieved_tops, 3), "peak": round(INT32_PEAK_TOPS, 2),
-                     "unit": "Tint32op/s", "frac": round(achieved_tops / INT32_PEAK_TOPS, 4), "traffic": traffic,
-                     "launch_us": round(d["us"], 3), "ops_per_butterfly": butterfly_word_ops(W_words),
-                     "valu_issue": valu_issue,
-                     "algorithmic_bytes": d["bytes"],
-                     "hbm_gbs_algorithmic": round(d["bytes"] / (d["us"] * 1e-6) / 1e9, 1),
-                     "passes_us": {str(k): round(v["us"], 3) for k, v in passes.items()}},
-        "wall_s_timed_region": round(wall, 4),
-        # host time to issue one step (7 library calls through the Python
-        # binding); close to ms_per_step means the plain step is bound by
-        # call submission rather than by the GPU
-        "host_issue_us_per_step": round(t_enq / args.steps * 1e6, 2),
-        "plain_step_graph": {"us_per_step": round(graph_us, 2), "ntt_s": round(2.0 / (graph_us * 1e-6), 1),
-                             "note": "the same step (7 launches, one per op) captured once in a hipGraph"},
-    }
-    if args.copy_calibration_mib:
-        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings scale
-        # the counters of the transform kernels to bytes
-        nbytes = args.copy_calibration_mib << 20
-        src = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda").fill_(3)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        res["copy_calibration_bytes"] = nbytes
-    if not args.no_cpu_baseline:
-        progress("cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline(wl)
-    plan.destroy()
-    print(json.dumps(res), flush=True)
+    return {"bound": "alu",
+            "kernel": f"forward pass {dom} ({'column' if dom == 1 else 'row'} tiles), N=2^16, 124-bit, "
+                      f"batch {RB}, one launch ({'large-batch' if large else 'single-transform'} configuration)",
+            "achieved": round(achieved, 3), "peak": round(INT32_PEAK_TOPS, 2),
+            "unit": "Tint32op/s", "frac": round(achieved / INT32_PEAK_TOPS, 4), "traffic": traffic,
+            "ops_per_butterfly": model_ops,
+            "minimal": {"ops_per_butterfly": butterfly_word_ops(W_words), "achieved": round(achieved_min, 3),
+                        "frac": round(achieved_min / INT32_PEAK_TOPS, 4)},
+            "launch_us": round(d["us"], 3), "butterflies": d["butterflies"],
+            "valu_issue": valu_issue,
+            "algorithmic_bytes": d["bytes"],
+            "hbm_gbs_algorithmic": round(d["bytes"] / (d["us"] * 1e-6) / 1e9, 1),
+            "passes_us": {str(k): round(v["us"], 3) for k, v in passes.items()}}
 
 
 if __name__ == "__main__":
