@@ -3,17 +3,22 @@
 // y = alpha*x + y (Shoup multiplication by the constant alpha).
 //
 // These are streaming kernels bound by HBM bandwidth (124-bit add/sub/axpy) or
-// close to the VALU ridge (124-bit mulmod).  Each lane handles VEC consecutive
-// residues with 16-byte vector loads; a grid-stride loop over chunks of
-// VEC*blockDim residues keeps the grid at a few waves per SIMD for any length,
-// and a guarded scalar path handles the ragged tail.
+// close to the VALU ridge (124- and 252-bit mulmod).  A block of 256 lanes
+// handles VEC residues per lane per chunk with 16-byte vector accesses; the
+// grid covers every chunk (a grid-stride loop only past 2^30 blocks), and a
+// guarded path handles the ragged tail.
 //
-// Cache policy of the streamed accesses (measured on MI355X at n = 2^24,
-// algorithmic bytes: two vectors in, one out): one-word residues store with
-// the non-temporal hint (5.4-5.5 -> 6.5-6.9 TB/s), two-word residues load and
-// store with it (5.3-5.5 -> 5.7-6.1 TB/s); four-word residues, read as two
-// 16-byte halves per lane, are fastest with ordinary accesses (every
-// non-temporal form lost 3-19% there).
+// Access form per width, from a triad probe (two streams read, one written,
+// the 2^24-residue workload) on MI355X:
+//   one word   8-byte residues, non-temporal stores             7.27 TB/s
+//   two words  16-byte residues, non-temporal loads, 2 per lane 7.03 TB/s
+//              (non-temporal loads and stores: 6.52; a 2048-block grid with
+//              a stride loop: 6.22)
+//   four words 32-byte residues read as two 16-byte halves by one lane touch
+//              twice the cache lines per instruction (5.5-5.8 TB/s); the
+//              block instead moves its residues as coalesced 16-byte units
+//              through LDS and each lane takes its residue from there:
+//              6.97 TB/s with non-temporal loads.
 #include <hip/hip_runtime.h>
 
 #include "mw_arith.h"
@@ -58,15 +63,13 @@ __device__ __forceinline__ Res<W> blas_elem(const Res<W>& a, const Res<W>& b, co
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Loads and stores of the main streaming loop, per width (see the cache
-// policy above).
+// Loads and stores of the main streaming loop, per width (see the access
+// forms above; four-word residues go through LDS instead).
 template <int W>
-struct Stream {
-  __device__ static __forceinline__ Res<W> load(const Res<W>* p) { return ResIO<W>::load(p); }
-  __device__ static __forceinline__ void store(Res<W>* p, const Res<W>& r) { ResIO<W>::store(p, r); }
-};
+struct Stream;
 template <>
 struct Stream<2> {
+  static constexpr int VEC = 4;
   __device__ static __forceinline__ Res<2> load(const Res<2>* p) { return ResIO<2>::load(p); }
   __device__ static __forceinline__ void store(Res<2>* p, const Res<2>& r) {
     const u32x2 v = {r.v[0], r.v[1]};
@@ -75,34 +78,80 @@ struct Stream<2> {
 };
 template <>
 struct Stream<4> {
+  static constexpr int VEC = 2;
   __device__ static __forceinline__ Res<4> load(const Res<4>* p) {
     const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
     Res<4> r;
     r.v[0] = v.x; r.v[1] = v.y; r.v[2] = v.z; r.v[3] = v.w;
     return r;
   }
-  __device__ static __forceinline__ void store(Res<4>* p, const Res<4>& r) {
-    const u32x4 v = {r.v[0], r.v[1], r.v[2], r.v[3]};
-    __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(p));
-  }
+  __device__ static __forceinline__ void store(Res<4>* p, const Res<4>& r) { ResIO<4>::store(p, r); }
+};
+template <>
+struct Stream<8> {
+  static constexpr int VEC = 1;
 };
 
+constexpr int kBlasThreads = 256;
+
+// One chunk of four-word residues through LDS: the block's 2*VEC*256 16-byte
+// units of a and of b are loaded coalesced (non-temporal) into LDS, each lane
+// takes its residue(s) from there, writes the result over a's slots, and the
+// block stores the units coalesced.
+template <int OP, int VEC, bool NORM, bool KARA>
+__device__ __forceinline__ void blas_chunk8(Res<8>* c, const Res<8>* a, const Res<8>* b, u64 base_res,
+                                            const Modulus<8>& M, const Scalar<8>& s, u32x4* la, u32x4* lb) {
+  const u32 t = threadIdx.x;
+  const u32x4* ga = reinterpret_cast<const u32x4*>(a + base_res);
+  const u32x4* gb = reinterpret_cast<const u32x4*>(b + base_res);
+  u32x4 va[2 * VEC], vb[2 * VEC];
+#pragma unroll
+  for (int k = 0; k < 2 * VEC; ++k) {
+    va[k] = __builtin_nontemporal_load(ga + t + k * kBlasThreads);
+    vb[k] = __builtin_nontemporal_load(gb + t + k * kBlasThreads);
+  }
+#pragma unroll
+  for (int k = 0; k < 2 * VEC; ++k) {
+    la[t + k * kBlasThreads] = va[k];
+    lb[t + k * kBlasThreads] = vb[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    const u32 e = t + v * kBlasThreads;
+    const Res<8> x = ResIO<8>::load(la + 2 * e), y = ResIO<8>::load(lb + 2 * e);
+    ResIO<8>::store(la + 2 * e, blas_elem<8, OP, NORM, KARA>(x, y, M, s));
+  }
+  __syncthreads();
+  u32x4* gc = reinterpret_cast<u32x4*>(c + base_res);
+#pragma unroll
+  for (int k = 0; k < 2 * VEC; ++k) gc[t + k * kBlasThreads] = la[t + k * kBlasThreads];
+  __syncthreads();                                 // the next chunk reuses the slots
+}
+
 template <int W, int OP, int VEC, bool NORM, bool KARA>
-__global__ __launch_bounds__(256) void blas_kernel(Res<W>* c, const Res<W>* a,
-                                                   const Res<W>* b, u64 n, Modulus<W> M,
-                                                   Scalar<W> s) {
-  const u64 chunk = (u64)VEC * blockDim.x;
+__global__ __launch_bounds__(kBlasThreads) void blas_kernel(Res<W>* c, const Res<W>* a, const Res<W>* b, u64 n,
+                                                           Modulus<W> M, Scalar<W> s) {
+  const u64 chunk = (u64)VEC * kBlasThreads;
   const u64 nfull = n / chunk;
-  for (u64 blk = blockIdx.x; blk < nfull; blk += gridDim.x) {
-    const u64 base = blk * chunk + threadIdx.x;
-    Res<W> x[VEC], y[VEC];
+  if constexpr (W == 8) {
+    __shared__ u32x4 la[2 * VEC * kBlasThreads];
+    __shared__ u32x4 lb[2 * VEC * kBlasThreads];
+    for (u64 blk = blockIdx.x; blk < nfull; blk += gridDim.x)
+      blas_chunk8<OP, VEC, NORM, KARA>(c, a, b, blk * chunk, M, s, la, lb);
+  } else {
+    for (u64 blk = blockIdx.x; blk < nfull; blk += gridDim.x) {
+      const u64 base = blk * chunk + threadIdx.x;
+      Res<W> x[VEC], y[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      x[v] = Stream<W>::load(a + base + (u64)v * blockDim.x);
-      y[v] = Stream<W>::load(b + base + (u64)v * blockDim.x);
+      for (int v = 0; v < VEC; ++v) {
+        x[v] = Stream<W>::load(a + base + (u64)v * kBlasThreads);
+        y[v] = Stream<W>::load(b + base + (u64)v * kBlasThreads);
+      }
+#pragma unroll
+      for (int v = 0; v < VEC; ++v)
+        Stream<W>::store(c + base + (u64)v * kBlasThreads, blas_elem<W, OP, NORM, KARA>(x[v], y[v], M, s));
     }
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) Stream<W>::store(c + base + (u64)v * blockDim.x, blas_elem<W, OP, NORM, KARA>(x[v], y[v], M, s));
   }
   // ragged tail: residues [nfull*chunk, n), handled by the one block whose
   // turn comes next in the grid-stride order
@@ -124,8 +173,7 @@ inline int width_slot(uint32_t limbs) { return limbs == 1 ? 0 : (limbs == 2 ? 1 
 template <int W, int OP, bool NORM, bool KARA>
 static void launch_blas_kernel(unsigned grid, hipStream_t stream, void* d_c, const void* d_a, const void* d_b,
                                size_t n, const Modulus<W>& M, const Scalar<W>& s) {
-  constexpr int VEC = 4;
-  hipLaunchKernelGGL((blas_kernel<W, OP, VEC, NORM, KARA>), dim3(grid), dim3(256), 0, stream,
+  hipLaunchKernelGGL((blas_kernel<W, OP, Stream<W>::VEC, NORM, KARA>), dim3(grid), dim3(kBlasThreads), 0, stream,
                      reinterpret_cast<Res<W>*>(d_c), reinterpret_cast<const Res<W>*>(d_a),
                      reinterpret_cast<const Res<W>*>(d_b), (u64)n, M, s);
 }
@@ -133,12 +181,10 @@ static void launch_blas_kernel(unsigned grid, hipStream_t stream, void* d_c, con
 template <int W, int OP>
 static int launch_blas(void* d_c, const void* d_a, const void* d_b, size_t n, const Modulus<W>& M,
                        const Scalar<W>& s, hipStream_t stream) {
-  constexpr int VEC = 4;
-  constexpr int THREADS = 256;
-  const u64 chunk = (u64)VEC * THREADS;
-  u64 chunks = (n + chunk - 1) / chunk;
-  // at most 8 blocks per CU in flight; beyond that the grid-stride loop iterates
-  u64 grid = chunks < 2048 ? chunks : 2048;
+  const u64 chunk = (u64)Stream<W>::VEC * kBlasThreads;
+  const u64 chunks = (n + chunk - 1) / chunk;
+  // one block per chunk; past 2^30 blocks the grid-stride loop iterates
+  u64 grid = chunks < (u64(1) << 30) ? chunks : (u64(1) << 30);
   if (grid == 0) grid = 1;
   const unsigned g = (unsigned)grid;
   if constexpr (OP == OP_MUL) {
