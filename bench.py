@@ -136,8 +136,10 @@ def time_graph(fn, stream, reps=20):
     return us
 
 
-def serving_leg(count, rate=20000.0, budget=1 << 30, spin_us=0):
-    """Open-loop Poisson stream through the serving runtime (inputs pre-staged).
+def serving_leg(count, rate=20000.0, budget=1 << 30, spin_us=0, modes=("slots", "resident")):
+    """Open-loop Poisson stream through the serving runtime (inputs pre-staged),
+    once per scheduling mode: "slots" (the host scheduler launches each batch
+    on a stream) and "resident" (the device-resident request loop).
 
     70% transforms (half forward, half inverse) with N = 2^e, e uniform in
     10..17; 30% BLAS (half mulmod, half axpymod) with length floor(2^u), u
@@ -171,19 +173,23 @@ def serving_leg(count, rate=20000.0, budget=1 << 30, spin_us=0):
         arrivals.append(j["t"] * 1e6)
     torch.cuda.synchronize()
     progress(f"serving: {len(plans)} plans, {len(bufs)} input buffers staged")
-    srv = mwntt.MwServer(budget, max_inflight=4, max_batch=64, spin_us=spin_us)
-    warm = min(2000, count)
-    srv.replay(reqs[:warm], [a - arrivals[0] for a in arrivals[:warm]])
-    lat, span = srv.replay(reqs, arrivals)
-    st = srv.stats()
-    srv.destroy()
+    out = {"requests": count, "offered_rate": rate, "hbm_budget": budget, "spin_us": spin_us}
+    for mode in modes:
+        srv = mwntt.MwServer(budget, max_inflight=4, max_batch=64, spin_us=spin_us, resident=mode == "resident")
+        warm = min(2000, count)
+        srv.replay(reqs[:warm], [a - arrivals[0] for a in arrivals[:warm]])
+        lat, span = srv.replay(reqs, arrivals)
+        st = srv.stats()
+        srv.destroy()
+        out[mode] = {"throughput_req_s": round(count / (span * 1e-6), 1),
+                     "p50_us": round(percentile(lat, 50), 2), "p99_us": round(percentile(lat, 99), 2),
+                     "mean_us": round(sum(lat) / len(lat), 2), "makespan_s": round(span * 1e-6, 4),
+                     "batches": st["batches"], "max_batch": st["max_batch_seen"], "pool_peak_bytes": st["pool_peak"],
+                     "resident_requests": st["resident_requests"], "resident_launches": st["resident_launches"]}
+        progress(f"serving ({mode}): p50 {out[mode]['p50_us']} us, p99 {out[mode]['p99_us']} us")
     for p in plans.values():
         p.destroy()
-    return {"requests": count, "offered_rate": rate, "hbm_budget": budget, "spin_us": spin_us,
-            "throughput_req_s": round(count / (span * 1e-6), 1),
-            "p50_us": round(percentile(lat, 50), 2), "p99_us": round(percentile(lat, 99), 2),
-            "mean_us": round(sum(lat) / len(lat), 2), "makespan_s": round(span * 1e-6, 4),
-            "batches": st["batches"] - 0, "max_batch": st["max_batch_seen"], "pool_peak_bytes": st["pool_peak"]}
+    return out
 
 
 def cpu_baseline(wl, budget_s=12.0):

@@ -294,6 +294,23 @@ typedef struct {
                              it keeps polling without sleeping for n
                              microseconds after its last action, 0 .. 100000
                              (lower latency for one busy host core) */
+  uint32_t resident;      /* 1: transform, product and BLAS requests of one-
+                             and two-word moduli (BLAS: n <= 2^22)
+                             run in a device-resident loop instead of kernel
+                             launches: one persistent kernel (launched with
+                             the first such request, leaving after 20 ms
+                             without work, relaunched on demand) takes them
+                             from a ring in mapped host memory and signals
+                             completion there; the other requests, and all of
+                             them in validate mode, keep the slot path.
+                             0: every request takes the slot path.  Ignored in
+                             a dry run. */
+  uint32_t resident_max_tiles; /* with resident: only requests of at most
+                             this many tiles (workgroup tasks: a BLAS tile is
+                             1024 residues, a transform's tiles are the
+                             batched executor's) go to the loop, the others
+                             keep the slot path; 0 = 16 (measured: past that
+                             the launched kernels are faster), at most 4096 */
 } mw_server_config;
 
 enum mw_request_op {
@@ -323,6 +340,8 @@ typedef struct {
   uint64_t queue_peak;          /* most requests waiting for admission at once */
   uint64_t inflight_peak;       /* most batches on the device at once */
   size_t pool_peak;             /* most budget bytes in use at once */
+  uint64_t resident_requests;   /* requests run by the device-resident loop */
+  uint64_t resident_launches;   /* launches of that loop */
 } mw_server_stats;
 
 /* Creates the server on the current device (allocates the budget as one

@@ -23,11 +23,12 @@ ARCH = "gfx950"
 
 SOURCES = ["mw_ntt_w8_fwd.hip", "mw_ntt_w8_inv.hip", "mw_ntt_w4_fwd.hip", "mw_ntt_w4_inv.hip",
            "mw_ntt_w2_fwd.hip", "mw_ntt_w2_inv.hip", "mw_ntt_ablation.hip",
-           "mw_exec.hip", "mw_blas.hip", "mw_ntt.hip", "mw_serve.hip", "mw_validate.hip", "mw_capi.cpp"]
+           "mw_exec.hip", "mw_resident.hip", "mw_blas.hip", "mw_ntt.hip", "mw_serve.hip", "mw_validate.hip",
+           "mw_capi.cpp"]
 # Sources whose kernels are scheduled for instruction-level parallelism: the
 # multi-word carry chains otherwise serialize on VCC with hazard wait states.
 ILP_SOURCES = {"mw_ntt_w8_fwd.hip", "mw_ntt_w8_inv.hip", "mw_ntt_w4_fwd.hip", "mw_ntt_w4_inv.hip",
-               "mw_ntt_w2_fwd.hip", "mw_ntt_w2_inv.hip", "mw_ntt_ablation.hip", "mw_exec.hip"}
+               "mw_ntt_w2_fwd.hip", "mw_ntt_w2_inv.hip", "mw_ntt_ablation.hip", "mw_exec.hip", "mw_resident.hip"}
 ILP_FLAGS = ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-DMWNTT_MIN_WAVES_PER_EU=3"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "mw_arith.h"
+#include "mw_blas_elem.h"
 #include "mw_common.h"
 #include "mw_tuned.h"
 #include "mw_validate.h"
@@ -29,36 +30,6 @@
 #include <atomic>
 
 namespace mw {
-
-enum BlasOp { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_AXPY = 3 };
-
-template <int W>
-struct Scalar {
-  u32 w[W];
-  u32 ws[W];
-};
-
-// NORM: products reduce on the scaled modulus (a modulus below the top of its
-// width class; a kernel of its own, so the full-width one keeps its code).
-// KARA: the full product by one level of Karatsuba (Eq. mulk).
-template <int W, int OP, bool NORM, bool KARA = false>
-__device__ __forceinline__ Res<W> blas_elem(const Res<W>& a, const Res<W>& b, const Modulus<W>& M,
-                                           const Scalar<W>& s) {
-  if constexpr (OP == OP_ADD) {
-    return addmod(a, b, M);
-  } else if constexpr (OP == OP_SUB) {
-    return submod(a, b, M);
-  } else if constexpr (OP == OP_MUL) {
-    return barrett_mul_t<W, NORM, KARA>(a, b, M);
-  } else {
-    // a = x, b = y: alpha*x in [0, 6q), + y in [0, 7q) -> canonical
-    Res<W> t = shoup_mul(a, s.w, s.ws, M);
-    t = add(t, b);
-    t = csub(t, M.q4);
-    t = csub(t, M.q2);
-    return csub(t, M.q);
-  }
-}
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));

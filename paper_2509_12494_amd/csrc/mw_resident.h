@@ -1,0 +1,136 @@
+// Device-resident request loop of the serving runtime: one persistent kernel
+// takes transform, product and BLAS requests of one- and two-word moduli from
+// a ring in mapped host memory and runs their tiles, so a request costs no
+// kernel launch.
+//
+// Protocol (host = the server's scheduler, device = the kernel):
+//  * The host writes entry e (global number) into ring slot e mod kResRing of
+//    the mapped host block, then publishes it by storing tail = e + 1.
+//  * Workgroup 0 of the kernel (the dispatcher) polls tail.  For each new
+//    entry it copies the descriptor into device memory and writes one word
+//    per tile into the tile ring: word g (global tile number) is
+//    g << 24 | slot << 12 | tile, stored at g mod kResTileRing.
+//  * Every other workgroup (a worker) claims the next global tile number g
+//    with an atomic add, waits until word g carries tag g, then runs that
+//    tile.  A tile of phase k > 0 first waits until the entry's completed-tile
+//    count covers every tile of the earlier phases (tiles are numbered phase
+//    by phase, so the earliest unfinished tile never waits on a later one and
+//    the loop cannot deadlock).  The workgroup that completes the entry's last
+//    tile stores seq + 1 (bit 63: a dependency wait timed out) into the
+//    slot's done word in host memory, which the host polls.
+//  * Tiles of different workgroups meet through device memory on different
+//    XCDs, whose L2 caches are not coherent with each other within a kernel:
+//    a tile's stores are released at agent scope (L2 write-back) before its
+//    count is raised, and a tile acquires at agent scope (L2 invalidate)
+//    before it reads what other tiles or the dispatcher wrote.  Each is done
+//    once per workgroup, by one lane after every wave has waited for its own
+//    stores: these cache operations act on the XCD's whole L2 and queue
+//    behind each other, and one per wave made a 64-tile request take twice
+//    as long.
+//  * Every wait is bounded: workers leave when the dispatcher sets the stop
+//    word, or when its heartbeat has not moved for the stall bound (a
+//    dispatcher that is not running); the dispatcher leaves when the host
+//    asks it to (after draining) or when every entry it took is complete and
+//    no new one arrived for the idle time, and also when entries are pending
+//    but none has completed for the stall bound; a dependency wait gives up
+//    (marking the entry failed) after the wait bound.  The host relaunches
+//    the kernel when it publishes an entry and finds the kernel gone, and
+//    fails the entries an ended kernel took but did not complete.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "mw_blas_elem.h"
+#include "mw_exec.h"
+
+namespace mw {
+
+constexpr u32 kResRing = 1024;              // entries in the ring (power of two, <= 4096)
+constexpr u32 kResTileRing = 1u << 20;      // tile words (power of two)
+constexpr u32 kResMaxTiles = 4096;          // tiles per entry (12 bits of a tile word)
+constexpr u32 kResLds = 48 * 1024;          // dynamic LDS of a worker: the largest tile it takes
+constexpr u32 kResBlasChunk = 4 * 256;      // residues per BLAS tile
+constexpr u32 kResMaxLog2N = 17;            // largest transform the loop takes (a plan's largest)
+// By default, requests of at most this many tiles go to the loop, larger
+// ones keep the slot path (mw_server_config.resident_max_tiles changes it).  Every tile pays an L2 invalidate and an L2 write-back on its
+// XCD, and the loop runs the run-time line engine, so past a few dozen tiles
+// the launched kernels (specialised tiles, no per-tile cache maintenance) are
+// faster.  Measured on MI355X, 20 K requests/s Poisson stream, p50 in us
+// (loop vs slot path): BLAS 2^10 (1 tile) 20.4 vs 23.7, 2^14 (16 tiles)
+// 25.2 vs 24.2, 2^16 (64) 32.7 vs 24.6; 124-bit NTT 2^10 (2 tiles) 29.3 vs
+// 33.7, 2^13 (16) 34.3 vs 36.0, 2^14 (32) 36.2 vs 36.8, 2^17 (256) 69.7 vs
+// 40.1.
+constexpr u32 kResRouteTiles = 16;
+constexpr u64 kResTagMask = (u64(1) << 40) - 1;
+
+enum { RES_NTT = 0, RES_BLAS = 1 };
+
+// One request.  Transforms and products: `job` (as the batched executor's)
+// and the constants of its width; BLAS: op, length, operands and the modulus
+// (m4.M / m2.M) with the axpy scalar.
+struct alignas(16) ResEntry {
+  u64 seq;              // global entry number
+  u32 kind;             // RES_NTT / RES_BLAS
+  u32 limbs;            // 1 or 2
+  u32 total;            // tiles
+  u32 nphases;
+  u32 prefix[4];        // tiles before phase k; prefix[nphases] = total
+  u32 blas_op;          // OP_ADD .. OP_AXPY (c = alpha*a + b for axpy)
+  u32 pad0;
+  u64 n;                // BLAS length
+  u64 a, b, c;          // BLAS operands and output
+  JobDesc job;
+  ModConst<4> m4;       // constants of a two-word modulus
+  ModConst<2> m2;       // one-word
+  Scalar<4> s4;
+  Scalar<2> s2;
+};
+static_assert(sizeof(ResEntry) % 16 == 0, "entries are copied in 16-byte units");
+
+// Device control words, reset by the host before each launch.
+struct ResCtl {
+  u64 gcursor;          // next global tile number to claim
+  u32 stop;             // dispatcher -> workers: leave
+  u32 exited;           // workers that have left
+  u64 completed;        // entries completed (cumulative over launches)
+  u32 error;            // a dependency wait timed out
+  u32 beat;             // dispatcher's heartbeat, raised on every poll
+};
+
+// Device memory of the loop (one allocation).
+struct ResDevBlock {
+  ResCtl ctl;
+  u32 dcount[kResRing];           // tiles completed of the slot's entry
+  u32 dfail[kResRing];            // the slot's entry had a failed wait
+  ResEntry dent[kResRing];        // descriptors, copied by the dispatcher
+  u64 tiles[kResTileRing];        // tile words
+};
+static_assert(offsetof(ResDevBlock, dfail) == offsetof(ResDevBlock, dcount) + sizeof(u32) * kResRing,
+              "the per-slot counts are cleared as one range");
+
+// Mapped pinned host memory of the loop.
+struct ResHost {
+  u64 tail;                       // host: entries published
+  u64 consumed;                   // device: entries the dispatcher has taken
+  u32 stop;                       // host: leave once every entry is complete
+  u32 pad[3];
+  ResCtl ctl_init;                // staging of the control reset before a launch
+  u64 done[kResRing];             // device: seq + 1 of the slot's last completed entry
+  ResEntry ring[kResRing];
+};
+
+struct ResParams {
+  ResHost* host;                  // device address of the mapped block
+  ResDevBlock* dev;
+  u64 start_entry;                // first entry this launch takes
+  u64 gstart;                     // global number of that entry's first tile
+  u64 idle_ticks;                 // dispatcher's idle time before it leaves (wall-clock ticks)
+  u64 wait_ticks;                 // bound of a dependency wait
+  u64 stall_ticks;                // bound without progress (see the protocol)
+};
+
+// Launches the loop with `grid` workgroups (workgroup 0 dispatches) on s.
+hipError_t resident_launch(const ResParams& p, u32 grid, hipStream_t s);
+
+}  // namespace mw

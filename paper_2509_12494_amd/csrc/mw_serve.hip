@@ -18,6 +18,7 @@
 #include <sys/prctl.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -32,6 +33,7 @@
 
 #include "mw_common.h"
 #include "mw_exec.h"
+#include "mw_resident.h"
 #include "mw_validate.h"
 
 namespace mw {
@@ -136,6 +138,8 @@ struct Req {
   double t_submit = 0, t_done = 0;
   double cost_us = 0;   // dry-run model
   ReqState state = RQ_QUEUED;
+  bool resident = false;   // runs in the device-resident loop
+  uint64_t res_seq = 0;    // its entry number there
 };
 
 struct Slot {
@@ -151,6 +155,51 @@ struct Slot {
 };
 
 bool is_ntt(uint32_t op) { return op <= MW_REQ_POLYMUL; }
+
+// Host side of the device-resident loop (mw_resident.h).
+struct Resident {
+  ResHost* H = nullptr;          // mapped pinned block, host address
+  ResHost* H_dev = nullptr;      // its device address
+  ResDevBlock* D = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ended = nullptr;    // recorded after each launch
+  bool launched = false;
+  bool broken = false;           // a launch failed: resident requests fail
+  uint32_t grid = 0;
+  uint32_t route_tiles = kResRouteTiles;   // requests of at most this many tiles go to the loop
+  uint64_t idle_ticks = 0, wait_ticks = 0, stall_ticks = 0;
+  double last_query_us = 0;      // last check whether the loop has ended
+  uint64_t published = 0;        // entries published
+  uint64_t gpub = 0;             // tiles published
+  uint64_t tiles_out = 0;        // tiles of published entries not yet complete
+  std::vector<uint64_t> tile_start;     // per ring slot: global number of its entry's first tile
+  std::vector<uint64_t> slot_ticket;    // per ring slot: ticket of its entry in flight, 0 if free
+  std::vector<uint32_t> slot_tiles;
+  std::vector<uint32_t> live;           // ring slots in flight
+  // Barrett and Shoup constants of BLAS moduli, by (q, limbs)
+  std::map<std::array<uint64_t, 3>, ModConst<4>> mod4;
+  std::map<std::array<uint64_t, 3>, ModConst<2>> mod2;
+  // tiles of a transform or product request, by (log2 N, limbs, job op)
+  std::map<std::array<uint32_t, 3>, uint32_t> job_tiles;
+};
+
+// Tiles the batched executor splits a transform or product on `plan` into
+// (they depend on N, the width and the operation only).
+uint32_t ntt_tiles(Resident& X, ntt_plan_t plan, uint32_t log2n, uint32_t limbs, uint32_t op) {
+  const std::array<uint32_t, 3> key = {log2n, limbs, op};
+  auto it = X.job_tiles.find(key);
+  if (it != X.job_tiles.end()) return it->second;
+  if (it != X.job_tiles.end()) return it->second;
+  ntt_job j;
+  j.plan = plan;
+  j.op = op;
+  j.in = j.in2 = j.out = reinterpret_cast<void*>(kAlign);   // placeholders: nothing is read
+  ExecPlan P;
+  uint32_t tiles = UINT32_MAX;
+  if (exec_build(&j, 1, P) == MW_OK) tiles = (uint32_t)P.items.size() + (uint32_t)P.items8.size();
+  X.job_tiles.emplace(key, tiles);
+  return tiles;
+}
 
 }  // namespace
 
@@ -170,6 +219,7 @@ struct mw_server_s {
   // scheduler appends every completed ticket
   bool track_done = false;
   std::deque<uint64_t> done_fifo;
+  Resident res;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::thread sched;
@@ -250,6 +300,290 @@ bool launch_batch(mw_server_s* S, Slot& slot, const std::vector<uint64_t>& batch
   return hipEventRecord(slot.done, slot.stream) == hipSuccess;
 }
 
+// ---- device-resident loop ------------------------------------------------
+
+// Fills ring entry E (number e) for an admitted request.  Status as mwntt.h.
+int res_fill(mw_server_s* S, const Req& R, ResEntry& E, uint64_t e) {
+  std::memset(&E, 0, sizeof(E));
+  E.seq = e;
+  if (is_ntt(R.r.op)) {
+    ntt_job j;
+    j.plan = R.r.plan;
+    j.op = R.r.op == MW_REQ_NTT_FORWARD ? NTT_JOB_FORWARD
+                                        : (R.r.op == MW_REQ_NTT_INVERSE ? NTT_JOB_INVERSE : NTT_JOB_POLYMUL);
+    j.in = R.r.in;
+    j.in2 = R.r.op == MW_REQ_POLYMUL ? R.r.in2 : nullptr;
+    j.out = pool_ptr(S, R.out_off);
+    ExecPlan plan;
+    const int st = exec_build(&j, 1, plan);
+    if (st != MW_OK) return st;
+    JobDesc& d = plan.jobs[0];
+    d.scratch = (u64)pool_ptr(S, R.scratch_off);
+    uint32_t total = 0;
+    for (u32 k = 0; k < d.nphases; ++k) {
+      E.prefix[k] = total;
+      total += d.tiles[k];
+      if (plan.phase_lds[k] > kResLds) return MW_ESIZE;
+    }
+    if (total > kResMaxTiles || d.limbs > 2) return MW_ESIZE;
+    E.prefix[d.nphases] = total;
+    E.kind = RES_NTT;
+    E.limbs = d.limbs;
+    E.total = total;
+    E.nphases = d.nphases;
+    E.job = d;
+    E.m4 = plan.m4[0];
+    E.m2 = plan.m2[0];
+    return MW_OK;
+  }
+  const uint32_t limbs = R.r.limbs;
+  const uint64_t tiles = (R.r.n + kResBlasChunk - 1) / kResBlasChunk;
+  if (limbs > 2 || tiles > kResMaxTiles) return MW_ESIZE;
+  E.kind = RES_BLAS;
+  E.limbs = limbs;
+  E.total = (uint32_t)tiles;
+  E.nphases = 1;
+  E.prefix[1] = E.total;
+  E.blas_op = R.r.op == MW_REQ_VEC_ADDMOD ? OP_ADD
+              : R.r.op == MW_REQ_VEC_SUBMOD ? OP_SUB
+              : R.r.op == MW_REQ_VEC_MULMOD ? OP_MUL : OP_AXPY;
+  E.n = R.r.n;
+  E.a = (u64)R.r.in;
+  E.b = (u64)R.r.in2;
+  E.c = (u64)pool_ptr(S, R.out_off);
+  const std::array<uint64_t, 3> key = {R.r.q[0], limbs == 2 ? R.r.q[1] : 0, limbs};
+  if (limbs == 2) {
+    auto it = S->res.mod4.find(key);
+    if (it == S->res.mod4.end()) {
+      ModConst<4> c = {};
+      make_modulus<4>(R.r.q, 2, c.M);
+      it = S->res.mod4.emplace(key, c).first;
+    }
+    E.m4 = it->second;
+    if (E.blas_op == OP_AXPY && make_scalar<4>(R.r.alpha, R.r.q, 2, E.s4.w, E.s4.ws) != MW_OK) return MW_EINVAL;
+  } else {
+    auto it = S->res.mod2.find(key);
+    if (it == S->res.mod2.end()) {
+      ModConst<2> c = {};
+      make_modulus<2>(R.r.q, 1, c.M);
+      it = S->res.mod2.emplace(key, c).first;
+    }
+    E.m2 = it->second;
+    if (E.blas_op == OP_AXPY && make_scalar<2>(R.r.alpha, R.r.q, 1, E.s2.w, E.s2.ws) != MW_OK) return MW_EINVAL;
+  }
+  return MW_OK;
+}
+
+void complete(mw_server_s* S, uint64_t tk, Req& R, bool failed) {
+  R.state = failed ? RQ_FAILED : RQ_DONE;
+  R.t_done = now_us();
+  S->pool.release(R.scratch_off, R.scratch_bytes);
+  R.scratch_bytes = 0;
+  ++S->stats.completed;
+  if (S->track_done) S->done_fifo.push_back(tk);
+}
+
+bool res_retire(mw_server_s* S);
+
+// Fails the loop's entries in flight whose number is below `bound`.
+void res_fail_live(mw_server_s* S, uint64_t bound) {
+  Resident& X = S->res;
+  for (size_t k = 0; k < X.live.size();) {
+    const uint32_t slot = X.live[k];
+    const uint64_t tk = X.slot_ticket[slot];
+    Req& R = S->reqs[tk];
+    if (R.res_seq >= bound) {
+      ++k;
+      continue;
+    }
+    complete(S, tk, R, true);
+    X.tiles_out -= X.slot_tiles[slot];
+    X.slot_ticket[slot] = 0;
+    X.live[k] = X.live.back();
+    X.live.pop_back();
+  }
+  S->cv_done.notify_all();
+}
+
+// Keeps the loop running while a published entry has not been taken: a loop
+// that has ended is relaunched from the first entry it did not take.  With
+// check_end it also looks whether the loop has ended with entries it took
+// still incomplete (a stall bound ran out), and fails them.  false: a launch
+// failed (the loop is marked broken).
+bool res_ensure_running(mw_server_s* S, bool check_end) {
+  Resident& X = S->res;
+  uint64_t start = 0;
+  if (X.launched) {
+    start = __atomic_load_n(&X.H->consumed, __ATOMIC_ACQUIRE);
+    const bool untaken = start < X.published;
+    if (!untaken && !check_end) return true;
+    X.last_query_us = now_us();
+    if (hipEventQuery(X.ended) == hipErrorNotReady) return true;
+    // the loop has ended: an entry it took and did not complete never will
+    res_retire(S);
+    res_fail_live(S, start);
+    if (!untaken) return true;
+  }
+  const uint64_t gstart = start < X.published ? X.tile_start[start & (kResRing - 1)] : X.gpub;
+  ResCtl c = {};
+  c.gcursor = gstart;
+  c.completed = start;
+  X.H->ctl_init = c;
+  ResParams p;
+  p.host = X.H_dev;
+  p.dev = X.D;
+  p.start_entry = start;
+  p.gstart = gstart;
+  p.idle_ticks = X.idle_ticks;
+  p.wait_ticks = X.wait_ticks;
+  p.stall_ticks = X.stall_ticks;
+  // the per-slot counts start from zero: an entry failed by an ended loop
+  // may have left its count part-way
+  if (hipMemcpyAsync(&X.D->ctl, &X.H->ctl_init, sizeof(ResCtl), hipMemcpyHostToDevice, X.stream) != hipSuccess ||
+      hipMemsetAsync(X.D->dcount, 0, sizeof(X.D->dcount) + sizeof(X.D->dfail), X.stream) != hipSuccess ||
+      resident_launch(p, X.grid, X.stream) != hipSuccess || hipEventRecord(X.ended, X.stream) != hipSuccess) {
+    X.broken = true;
+    return false;
+  }
+  X.launched = true;
+  ++S->stats.resident_launches;
+  return true;
+}
+
+// Publishes the request at the head of the queue into the loop's ring.
+// Returns false (and leaves it queued) when the ring, the tile ring or the
+// memory budget has no room for it yet.
+bool res_admit_head(mw_server_s* S) {
+  Resident& X = S->res;
+  const uint64_t tk = S->queue.front();
+  Req& R = S->reqs[tk];
+  const uint64_t e = X.published;
+  const uint32_t slot = (uint32_t)(e & (kResRing - 1));
+  if (X.broken) {
+    S->queue.pop_front();
+    R.state = RQ_RUNNING;
+    complete(S, tk, R, true);
+    S->cv_done.notify_all();
+    return true;
+  }
+  if (X.slot_ticket[slot] || X.tiles_out + kResMaxTiles > kResTileRing) return false;
+  size_t oo = 0, so = 0;
+  if (!S->pool.alloc(R.out_bytes, &oo)) return false;
+  if (!S->pool.alloc(R.scratch_bytes, &so)) {
+    S->pool.release(oo, R.out_bytes);
+    return false;
+  }
+  R.out_off = oo;
+  R.scratch_off = so;
+  R.state = RQ_RUNNING;
+  S->queue.pop_front();
+  S->stats.pool_peak = std::max(S->stats.pool_peak, S->pool.used());
+  ResEntry& E = X.H->ring[slot];
+  if (res_fill(S, R, E, e) != MW_OK) {
+    complete(S, tk, R, true);
+    S->cv_done.notify_all();
+    return true;
+  }
+  R.res_seq = e;
+  X.tile_start[slot] = X.gpub;
+  X.gpub += E.total;
+  X.tiles_out += E.total;
+  X.slot_ticket[slot] = tk;
+  X.slot_tiles[slot] = E.total;
+  X.live.push_back(slot);
+  X.published = e + 1;
+  ++S->stats.resident_requests;
+  __atomic_store_n(&X.H->tail, X.published, __ATOMIC_RELEASE);
+  // the loop cannot run: nothing in flight will complete
+  if (!res_ensure_running(S, false)) res_fail_live(S, UINT64_MAX);
+  return true;
+}
+
+// Retires completed entries of the loop; true if any completed.
+bool res_retire(mw_server_s* S) {
+  Resident& X = S->res;
+  bool any = false;
+  for (size_t k = 0; k < X.live.size();) {
+    const uint32_t slot = X.live[k];
+    const uint64_t tk = X.slot_ticket[slot];
+    Req& R = S->reqs[tk];
+    const uint64_t d = __atomic_load_n(&X.H->done[slot], __ATOMIC_ACQUIRE);
+    if ((d & ~(uint64_t(1) << 63)) != R.res_seq + 1) {
+      ++k;
+      continue;
+    }
+    complete(S, tk, R, (d >> 63) != 0);
+    X.tiles_out -= X.slot_tiles[slot];
+    X.slot_ticket[slot] = 0;
+    X.live[k] = X.live.back();
+    X.live.pop_back();
+    any = true;
+  }
+  return any;
+}
+
+// Launches the run of slot-path requests at the head of the queue (up to
+// max_batch, stopping at a request for the resident loop or one whose memory
+// does not fit) on a free slot; false if nothing was launched.
+bool admit_slot_batch(mw_server_s* S) {
+  if (S->inflight >= S->cfg.max_inflight) return false;
+  Slot* slot = nullptr;
+  for (Slot& s : S->slots)
+    if (!s.busy) {
+      slot = &s;
+      break;
+    }
+  if (!slot) return false;
+  std::vector<uint64_t> batch;
+  while (!S->queue.empty() && batch.size() < S->cfg.max_batch) {
+    Req& R = S->reqs[S->queue.front()];
+    if (R.resident) break;
+    size_t oo = 0, so = 0;
+    if (!S->pool.alloc(R.out_bytes, &oo)) break;
+    if (!S->pool.alloc(R.scratch_bytes, &so)) {
+      S->pool.release(oo, R.out_bytes);
+      break;
+    }
+    R.out_off = oo;
+    R.scratch_off = so;
+    R.state = RQ_RUNNING;
+    batch.push_back(S->queue.front());
+    S->queue.pop_front();
+  }
+  if (batch.empty()) return false;   // the oldest request waits for memory
+  slot->busy = true;
+  ++S->inflight;
+  ++S->stats.batches;
+  S->stats.max_batch_seen = std::max<uint64_t>(S->stats.max_batch_seen, batch.size());
+  S->stats.inflight_peak = std::max<uint64_t>(S->stats.inflight_peak, S->inflight);
+  S->stats.pool_peak = std::max(S->stats.pool_peak, S->pool.used());
+  if (!launch_batch(S, *slot, batch)) {
+    // the batch could not be launched: part of it may already be queued on
+    // the slot's stream (kernels, the descriptor copy from the slot's
+    // pinned block), so wait for the stream before its scratch, outputs
+    // and pinned block are reused; then fail its requests, free the slot
+    if (!S->cfg.dry_run) (void)hipStreamSynchronize(slot->stream);
+    for (uint64_t tk : batch) complete(S, tk, S->reqs[tk], true);
+    slot->tickets.clear();
+    slot->busy = false;
+    --S->inflight;
+    S->cv_done.notify_all();
+  }
+  return true;
+}
+
+// Admits from the head of the queue: requests for the resident loop go into
+// its ring, runs of other requests to a slot, in arrival order.
+bool admit(mw_server_s* S) {
+  bool progress = false;
+  while (!S->queue.empty()) {
+    const bool ok = S->reqs[S->queue.front()].resident ? res_admit_head(S) : admit_slot_batch(S);
+    if (!ok) break;
+    progress = true;
+  }
+  return progress;
+}
+
 void scheduler(mw_server_s* S) {
   if (!S->cfg.dry_run) (void)hipSetDevice(S->device);
   // While batches run the loop re-checks their events every few microseconds
@@ -273,76 +607,27 @@ void scheduler(mw_server_s* S) {
         failed = done && e != hipSuccess;
       }
       if (!done) continue;
-      const double t = now_us();
-      for (uint64_t tk : slot.tickets) {
-        Req& R = S->reqs[tk];
-        R.state = failed ? RQ_FAILED : RQ_DONE;
-        R.t_done = t;
-        S->pool.release(R.scratch_off, R.scratch_bytes);
-        R.scratch_bytes = 0;
-        ++S->stats.completed;
-        if (S->track_done) S->done_fifo.push_back(tk);
-      }
+      for (uint64_t tk : slot.tickets) complete(S, tk, S->reqs[tk], failed);
       slot.tickets.clear();
       slot.busy = false;
       --S->inflight;
       progress = true;
     }
-    if (progress) S->cv_done.notify_all();
-    // admit and launch
-    while (S->inflight < S->cfg.max_inflight && !S->queue.empty()) {
-      Slot* slot = nullptr;
-      for (Slot& s : S->slots)
-        if (!s.busy) {
-          slot = &s;
-          break;
-        }
-      if (!slot) break;
-      std::vector<uint64_t> batch;
-      while (!S->queue.empty() && batch.size() < S->cfg.max_batch) {
-        Req& R = S->reqs[S->queue.front()];
-        size_t oo = 0, so = 0;
-        if (!S->pool.alloc(R.out_bytes, &oo)) break;
-        if (!S->pool.alloc(R.scratch_bytes, &so)) {
-          S->pool.release(oo, R.out_bytes);
-          break;
-        }
-        R.out_off = oo;
-        R.scratch_off = so;
-        R.state = RQ_RUNNING;
-        batch.push_back(S->queue.front());
-        S->queue.pop_front();
+    if (!S->res.live.empty()) {
+      if (res_retire(S)) progress = true;
+      // an entry published just as an idle loop left is taken by a new
+      // launch; now and then, look whether the loop ended on a stall
+      const size_t before = S->res.live.size();
+      if (before) {
+        const bool check_end = now_us() - S->res.last_query_us > 10000.0;
+        if (!res_ensure_running(S, check_end)) res_fail_live(S, UINT64_MAX);
+        if (S->res.live.size() != before) progress = true;
       }
-      if (batch.empty()) break;   // the oldest request waits for memory
-      slot->busy = true;
-      ++S->inflight;
-      ++S->stats.batches;
-      S->stats.max_batch_seen = std::max<uint64_t>(S->stats.max_batch_seen, batch.size());
-      S->stats.inflight_peak = std::max<uint64_t>(S->stats.inflight_peak, S->inflight);
-      S->stats.pool_peak = std::max(S->stats.pool_peak, S->pool.used());
-      if (!launch_batch(S, *slot, batch)) {
-        // the batch could not be launched: part of it may already be queued on
-        // the slot's stream (kernels, the descriptor copy from the slot's
-        // pinned block), so wait for the stream before its scratch, outputs
-        // and pinned block are reused; then fail its requests, free the slot
-        if (!S->cfg.dry_run) (void)hipStreamSynchronize(slot->stream);
-        for (uint64_t tk : batch) {
-          Req& R = S->reqs[tk];
-          R.state = RQ_FAILED;
-          R.t_done = now_us();
-          S->pool.release(R.scratch_off, R.scratch_bytes);
-          R.scratch_bytes = 0;
-          ++S->stats.completed;
-          if (S->track_done) S->done_fifo.push_back(tk);
-        }
-        slot->tickets.clear();
-        slot->busy = false;
-        --S->inflight;
-        S->cv_done.notify_all();
-      }
-      progress = true;
     }
-    if (S->stop && S->queue.empty() && S->inflight == 0) break;
+    if (progress) S->cv_done.notify_all();
+    if (admit(S)) progress = true;
+    const bool busy = S->inflight || !S->res.live.empty();
+    if (S->stop && S->queue.empty() && !busy) break;
     if (progress) {
       last_action = now_us();
     } else if (S->cfg.spin_us && now_us() - last_action < S->cfg.spin_us) {
@@ -351,8 +636,8 @@ void scheduler(mw_server_s* S) {
       std::this_thread::yield();
       lk.lock();
     } else {
-      // poll completions often while batches run, otherwise sleep until work
-      if (S->inflight) S->cv_work.wait_for(lk, std::chrono::microseconds(4));
+      // poll completions often while work runs, otherwise sleep until work
+      if (busy) S->cv_work.wait_for(lk, std::chrono::microseconds(4));
       else S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
     }
   }
@@ -360,6 +645,7 @@ void scheduler(mw_server_s* S) {
 
 int validate(mw_server_s* S, const mw_request& r, Req& R) {
   const uint32_t op = r.op;
+  bool fits_resident = false;
   if (op > MW_REQ_VEC_AXPYMOD || !r.in) return MW_EINVAL;
   if (is_ntt(op)) {
     if (!r.plan) return MW_EINVAL;
@@ -369,6 +655,10 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
     ModConst<2> c2;
     if (!plan_view(r.plan, v, c8, c4, c2) || v.variant) return MW_EINVAL;
     if (v.log2n < 6) return MW_ESIZE;
+    fits_resident = S->cfg.resident && v.limbs <= 2 && v.log2n <= kResMaxLog2N &&
+                    ntt_tiles(S->res, r.plan, v.log2n, v.limbs, op == MW_REQ_NTT_FORWARD ? NTT_JOB_FORWARD
+                                              : (op == MW_REQ_NTT_INVERSE ? NTT_JOB_INVERSE : NTT_JOB_POLYMUL)) <=
+                        S->res.route_tiles;
     if (op == MW_REQ_POLYMUL) {
       if (!r.in2) return MW_EINVAL;
       if (check_modulus(v.q, v.limbs) != MW_OK) return MW_EMODULUS;
@@ -388,9 +678,15 @@ int validate(mw_server_s* S, const mw_request& r, Req& R) {
     }
     R.out_bytes = round_up((size_t)8 * r.limbs * r.n);
     R.scratch_bytes = 0;
+    fits_resident = r.limbs <= 2 && r.n <= (uint64_t)S->res.route_tiles * kResBlasChunk;
     R.cost_us = 1.0 + (double)R.out_bytes / 4.0e4;
   }
   if (R.out_bytes + R.scratch_bytes > S->pool.size()) return MW_ENOMEM;
+  // the resident loop takes one- and two-word requests up to its tile limits;
+  // validate mode checks inputs on a slot's stream, so it keeps the slot path
+  if (S->cfg.resident && !S->cfg.dry_run && !validate_on()) {
+    R.resident = fits_resident;
+  }
   return MW_OK;
 }
 
@@ -401,8 +697,46 @@ void free_server(mw_server_s* S) {
     if (s.d_desc) (void)hipFree(s.d_desc);
     if (s.h_desc) (void)hipHostFree(s.h_desc);
   }
+  Resident& X = S->res;
+  if (X.stream) (void)hipStreamDestroy(X.stream);
+  if (X.ended) (void)hipEventDestroy(X.ended);
+  if (X.D) (void)hipFree(X.D);
+  if (X.H) (void)hipHostFree(X.H);
   if (S->pool_base) (void)hipFree(S->pool_base);
   delete S;
+}
+
+// Memory, stream and clock constants of the resident loop (no launch yet:
+// the first request launches it).
+int init_resident(mw_server_s* S) {
+  Resident& X = S->res;
+  int cus = 0, khz = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S->device) != hipSuccess || cus <= 0 || khz <= 0)
+    return MW_EDEVICE;
+  // two workgroups per compute unit (what its registers allow): workgroup 0
+  // dispatches, the others work
+  X.grid = 2 * (uint32_t)cus;
+  if (S->cfg.resident_max_tiles) X.route_tiles = S->cfg.resident_max_tiles;
+  X.idle_ticks = (uint64_t)khz * 20;      // 20 ms
+  X.wait_ticks = (uint64_t)khz * 2000;    // 2 s
+  X.stall_ticks = (uint64_t)khz * 5000;   // 5 s
+  X.tile_start.assign(kResRing, 0);
+  X.slot_ticket.assign(kResRing, 0);
+  X.slot_tiles.assign(kResRing, 0);
+  if (hipHostMalloc(reinterpret_cast<void**>(&X.H), sizeof(ResHost), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&X.D), sizeof(ResDevBlock)) != hipSuccess)
+    return MW_ENOMEM;
+  std::memset(X.H, 0, sizeof(ResHost));
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&X.H_dev), X.H, 0) != hipSuccess ||
+      hipMemset(X.D, 0, sizeof(ResDevBlock)) != hipSuccess ||
+      // no tile word may carry a valid tag before the dispatcher writes it
+      hipMemset(X.D->tiles, 0xff, sizeof(X.D->tiles)) != hipSuccess ||
+      hipStreamCreateWithFlags(&X.stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&X.ended, hipEventDisableTiming) != hipSuccess)
+    return MW_EDEVICE;
+  return MW_OK;
 }
 
 }  // namespace
@@ -411,7 +745,7 @@ extern "C" int mw_server_create(mw_server_t* out, const mw_server_config* cfg) {
   if (!out || !cfg) return MW_EINVAL;
   *out = nullptr;
   if (cfg->max_inflight < 1 || cfg->max_inflight > 16 || cfg->max_batch < 1 || cfg->max_batch > kMaxBatch ||
-      cfg->hbm_budget < kAlign || cfg->spin_us > 100000)
+      cfg->hbm_budget < kAlign || cfg->spin_us > 100000 || cfg->resident_max_tiles > kResMaxTiles)
     return MW_EINVAL;
   mw_server_s* S = new (std::nothrow) mw_server_s();
   if (!S) return MW_ENOMEM;
@@ -434,6 +768,7 @@ extern "C" int mw_server_create(mw_server_t* out, const mw_server_config* cfg) {
       if (hipMalloc(&s.d_desc, cap) != hipSuccess || hipHostMalloc(&s.h_desc, cap) != hipSuccess)
         st = MW_ENOMEM;
     }
+    if (st == MW_OK && cfg->resident) st = init_resident(S);
     if (st != MW_OK) {
       free_server(S);
       return st;
@@ -463,6 +798,9 @@ int submit_locked(mw_server_s* S, const mw_request* request, uint64_t* ticket) {
   ++S->stats.submitted;
   S->stats.queue_peak = std::max<uint64_t>(S->stats.queue_peak, S->queue.size());
   *ticket = t;
+  // a request for the resident loop that finds the queue empty is published
+  // by the submitting thread itself, without waiting for the scheduler
+  if (S->queue.size() == 1 && S->reqs[t].resident) res_admit_head(S);
   S->cv_work.notify_one();
   return MW_OK;
 }
@@ -602,6 +940,11 @@ extern "C" int mw_server_destroy(mw_server_t S) {
     S->cv_work.notify_all();
   }
   if (S->sched.joinable()) S->sched.join();
+  if (S->res.launched) {
+    // every request has completed: the loop leaves at its next look
+    __atomic_store_n(&S->res.H->stop, 1u, __ATOMIC_RELEASE);
+    (void)hipStreamSynchronize(S->res.stream);
+  }
   if (!S->cfg.dry_run) (void)hipDeviceSynchronize();
   free_server(S);
   return MW_OK;

@@ -122,6 +122,8 @@ def test_config_errors():
         mwntt.MwServer(1 << 20, max_batch=1000, dry_run=True)
     with pytest.raises(mwntt.MwError):
         mwntt.MwServer(1 << 20, spin_us=200000, dry_run=True)
+    with pytest.raises(mwntt.MwError):
+        mwntt.MwServer(1 << 20, resident=True, resident_max_tiles=4097, dry_run=True)
 
 
 def test_spinning_scheduler_completes_stream():
@@ -133,4 +135,16 @@ def test_spinning_scheduler_completes_stream():
     lat, span = srv.replay(reqs, arrivals)
     assert len(lat) == 300 and min(lat) >= 0 and span >= arrivals[-1]
     assert srv.stats()["completed"] == 300
+    srv.destroy()
+
+
+def test_resident_flag_ignored_in_dry_run():
+    # the device-resident loop needs a device: a dry run keeps the slot path
+    srv = mwntt.MwServer(1 << 24, max_inflight=2, max_batch=8, dry_run=True, resident=True)
+    tickets = [srv.submit(_req(1024 + i)) for i in range(20)]
+    for t in tickets:
+        srv.result(t, wait=True)
+        srv.release(t)
+    st = srv.stats()
+    assert st["completed"] == 20 and st["resident_requests"] == 0 and st["resident_launches"] == 0
     srv.destroy()

@@ -1,0 +1,177 @@
+"""The serving runtime's device-resident request loop on the GPU: one
+persistent kernel takes one- and two-word transform, product and BLAS requests
+of up to resident_max_tiles tiles from a ring in mapped host memory; the
+others keep the slot path.  Every result equals the same operation run alone
+through the plain entry points (and the oracle on sampled outputs): in a
+burst with the default routing and with every request in the loop, one
+request at a time (N = 2^6 .. 2^17, widths inside each class), mixed with
+four-word requests that keep the slot path, at the largest product (2^17,
+124-bit) and after the loop has left on idling and been launched again.  The
+routing follows the tile counts."""
+import time
+
+import pytest
+
+from paper_2509_12494_amd import mwntt
+
+from .gpu_util import announce, host_ints, require_gpu
+from .test_serve_gpu import _alone, _oracle_sample, _request, _workload
+
+pytestmark = pytest.mark.gpu
+
+BLAS_TILE = 1024       # residues per BLAS tile of the loop
+DEFAULT_TILES = 16     # the default routing bound
+
+
+def _tiles(it):
+    """Workgroup tiles of a request (a transform's or product's are the batched
+    executor's)."""
+    import torch
+    if it["plan"] is None:
+        return -(-it["n"] // BLAS_TILE)
+    op = {mwntt.MW_REQ_NTT_FORWARD: mwntt.NTT_JOB_FORWARD, mwntt.MW_REQ_NTT_INVERSE: mwntt.NTT_JOB_INVERSE,
+          mwntt.MW_REQ_POLYMUL: mwntt.NTT_JOB_POLYMUL}[it["op"]]
+    out = torch.empty_like(it["a"])
+    b = mwntt.NttBatch([(it["plan"], op, it["a"], it["b"] if op == mwntt.NTT_JOB_POLYMUL else None, out)])
+    t = b.info()["tiles"]
+    b.destroy()
+    return t
+
+
+def _in_loop(items, max_tiles):
+    bound = max_tiles or DEFAULT_TILES
+    return sum(1 for it in items if it["limbs"] <= 2 and _tiles(it) <= bound)
+
+
+def _run_and_check(srv, items, serial, sample_every=3):
+    import torch
+    tickets = [] if serial else [srv.submit(_request(it)) for it in items]
+    for i, it in enumerate(items):
+        t = srv.submit(_request(it)) if serial else tickets[i]
+        ptr, lat = srv.result(t, wait=True)
+        assert lat > 0
+        out = mwntt.copy_to_tensor(ptr, it["a"])
+        torch.cuda.synchronize()
+        srv.release(t)
+        assert torch.equal(out, _alone(it)), \
+            f"request {i} op {it['op']} n {it['n']} bits {it['q'].bit_length()}"
+        if i % sample_every == 0:
+            ks = [0, it["n"] - 1, (i * 37) % it["n"]]
+            got = host_ints(out, it["limbs"])
+            assert [got[k] for k in ks] == _oracle_sample(it, ks), f"request {i}"
+
+
+@pytest.mark.parametrize("wide,max_tiles", [(False, 0), (True, 0), (False, 4096), (True, 4096)])
+def test_resident_burst_matches_alone(wide, max_tiles):
+    """A burst of 56 requests (wide: a third of them 252-bit, which take the
+    slot path beside the loop; max_tiles 4096: every one- and two-word
+    request goes to the loop)."""
+    require_gpu()
+    items, plans = _workload(56, seed=71 + wide, wide=wide, log2_range=(10, 15))
+    srv = mwntt.MwServer(1 << 30, max_inflight=3, max_batch=16, resident=True, resident_max_tiles=max_tiles)
+    announce("resident burst", wide, max_tiles)
+    _run_and_check(srv, items, serial=False)
+    st = srv.stats()
+    assert st["completed"] == len(items)
+    expect = _in_loop(items, max_tiles)
+    assert st["resident_requests"] == expect and st["resident_launches"] >= 1
+    if max_tiles == 0:
+        assert 0 < expect < len(items)      # both paths in use
+    srv.destroy()
+    for p in plans.values():
+        p.destroy()
+
+
+def test_resident_one_at_a_time():
+    """Each request submitted after the previous one completed: transforms
+    and products at N = 2^6 .. 2^17 and BLAS at ragged lengths, at 33, 60,
+    80, 97 and 124 bits (Barrett on the scaled modulus below the top of a
+    class)."""
+    require_gpu()
+    items, plans = _workload(45, seed=83, log2_range=(6, 17), widths=[33, 60, 80, 97, 124])
+    srv = mwntt.MwServer(1 << 30, max_inflight=2, max_batch=8, resident=True, resident_max_tiles=4096)
+    announce("resident one at a time", len(items))
+    _run_and_check(srv, items, serial=True)
+    assert srv.stats()["resident_requests"] == len(items)
+    srv.destroy()
+    for p in plans.values():
+        p.destroy()
+
+
+def test_resident_largest_job():
+    """A 124-bit negacyclic product at N = 2^17 (the largest plan): 512 tiles
+    in three phases."""
+    require_gpu()
+    import torch
+    from paper_2509_12494_amd import workloads as W
+    q = W.find_prime(124, 97)
+    g = W.rng(97)
+    n = 1 << 17
+    A, B = W.uniform_residues(g, q, n, 2), W.uniform_residues(g, q, n, 2)
+    plan = mwntt.ntt_plan(17, q, 2)
+    it = dict(op=mwntt.MW_REQ_POLYMUL, q=q, limbs=2, n=n, plan=plan, A=A, B=B,
+              a=mwntt.to_device(A), b=mwntt.to_device(B), alpha=0)
+    srv = mwntt.MwServer(1 << 30, max_inflight=2, max_batch=8, resident=True, resident_max_tiles=4096)
+    announce("resident 2^17 product")
+    _run_and_check(srv, [it], serial=True, sample_every=1)
+    assert srv.stats()["resident_requests"] == 1
+    srv.destroy()
+    plan.destroy()
+    torch.cuda.synchronize()
+
+
+def test_resident_relaunch_after_idle():
+    """The loop leaves after 20 ms without work; the next request launches
+    it again, and results stay exact."""
+    require_gpu()
+    items, plans = _workload(21, seed=89, log2_range=(8, 12))
+    srv = mwntt.MwServer(1 << 30, max_inflight=2, max_batch=8, resident=True)
+    announce("resident relaunch")
+    for part in (items[:7], items[7:14], items[14:]):
+        _run_and_check(srv, part, serial=False)
+        time.sleep(0.1)
+    st = srv.stats()
+    assert st["resident_requests"] == len(items)
+    assert st["resident_launches"] >= 3
+    srv.destroy()
+    for p in plans.values():
+        p.destroy()
+
+
+def test_resident_replay_poisson():
+    """An open-loop Poisson replay at 20 K requests/s completes every request
+    through the loop."""
+    require_gpu()
+    import numpy as np
+    items, plans = _workload(400, seed=9, log2_range=(10, 14))
+    g = np.random.Generator(np.random.PCG64(4))
+    gaps = g.exponential(1e6 / 20000.0, size=len(items))
+    arrivals = list(np.cumsum(gaps) - gaps[0])
+    srv = mwntt.MwServer(1 << 30, max_inflight=4, max_batch=64, resident=True)
+    announce("resident replay", len(items))
+    lat, span = srv.replay([_request(it) for it in items], arrivals)
+    assert len(lat) == len(items) and min(lat) > 0
+    st = srv.stats()
+    assert st["completed"] == len(items) and st["resident_requests"] == _in_loop(items, 0)
+    srv.destroy()
+    for p in plans.values():
+        p.destroy()
+
+
+def test_resident_validate_mode_keeps_slot_path():
+    """In validate mode every request takes the slot path (its inputs are
+    checked on a slot's stream)."""
+    require_gpu()
+    items, plans = _workload(7, seed=101)
+    prev = mwntt.get_validate()
+    mwntt.set_validate(True)
+    try:
+        srv = mwntt.MwServer(1 << 30, max_inflight=2, max_batch=8, resident=True)
+        announce("resident validate mode")
+        _run_and_check(srv, items, serial=False)
+        assert srv.stats()["resident_requests"] == 0
+        srv.destroy()
+    finally:
+        mwntt.set_validate(prev)
+    for p in plans.values():
+        p.destroy()
