@@ -18,9 +18,11 @@ batch and its inverse, 256 fused products at 2^14, RNS products over eight
 primes, the 60-bit and 252-bit transforms and BLAS, BLAS at streaming sizes
 (2^24) against the HBM peak with both products of vec_mulmod (schoolbook and
 Karatsuba), the arithmetic variants of the 124-bit butterfly (the GPU analog
-of the paper's MQX ablation), and the serving replay; the roofline of the
-dominant kernel (with HBM traffic and VALU instructions from the committed
-rocprofv3 summary); and the CPU oracle's rate on a bounded sample.  --legs
+of the paper's MQX ablation), and the serving replay (host-scheduled slots and
+the device-resident loop); the roofline of the dominant kernel (with HBM
+traffic and VALU instructions from the committed rocprofv3 summary); the CPU
+oracle's rate on a bounded sample; and ``cpu_ref``, the scalar C++ baseline
+(unsigned __int128 double-words) on one core and on up to 16 cores.  --legs
 selects the legs after the plain step (the profiling commands run one leg).
 """
 import argparse
@@ -43,7 +45,7 @@ INT32_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # the remainder, and 2W word add/sub for the butterfly's sum and difference).
 PROFILE = os.path.join(ROOT, "profiles", "ntt_fwd_2e16_124bit_b64.md")
 KERNEL_SOURCES = ["mw_arith.h", "mw_butterfly.h", "mw_ntt_tile.h", "mw_ntt_kernels.inc", "mw_ntt.hip", "mw_tuned.h"]
-LEGS = ("batched", "sweep", "host", "mixed", "fused", "rns", "w60", "w252", "blas", "serving", "ablation",
+LEGS = ("batched", "sweep", "host", "mixed", "fused", "rns", "w60", "w252", "blas", "serving", "ablation", "cpu_ref",
         "roofline")
 
 
@@ -212,6 +214,48 @@ def cpu_baseline(wl, budget_s=12.0):
     return {"value": 1.0 / (per_output * n), "unit": "NTT/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} forward outputs A_k of one N=2^16 124-bit transform, each an O(N) sum "
                       f"from the definition ({dt:.1f} s), scaled to N outputs per transform"}
+
+
+def cpu_ref_leg(wl, budget_s=1.5):
+    """The scalar C++ baseline (cpu_ref: unsigned __int128 double-words,
+    schoolbook products, Barrett) on the same 2^16 124-bit polynomial: forward
+    transforms on one core and on every core this process may use (at most 16,
+    the host share of one GPU), and 124-bit vec_mulmod over 2^22 residues."""
+    import numpy as np
+    import cpu_ref
+    from paper_2509_12494_amd import workloads as W
+    threads = min(16, len(os.sched_getaffinity(0)))
+    q, limbs, log2n = wl.q, wl.limbs, wl.log2n
+    poly = np.ascontiguousarray(wl.data["poly"], dtype=np.uint64)
+    plan = cpu_ref.Plan(log2n, q, limbs)
+
+    def rate(fn, units):
+        fn()                                      # warm
+        done, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            fn()
+            done += units
+        return done / (time.perf_counter() - t0)
+
+    ntt_1 = rate(lambda: plan.transform(poly, threads=1), 1)
+    batch = np.concatenate([poly] * (2 * threads))
+    ntt_all = rate(lambda: plan.transform(batch, threads=threads), 2 * threads)
+    x = W.uniform_residues(W.rng(91), q, 1 << 22, limbs)
+    y = W.uniform_residues(W.rng(92), q, 1 << 22, limbs)
+    mul_1 = rate(lambda: cpu_ref.blas("mul", x, y, q, limbs, threads=1), 1 << 22)
+    mul_all = rate(lambda: cpu_ref.blas("mul", x, y, q, limbs, threads=threads), 1 << 22)
+    plan.destroy()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"kind": "cpu_ref (scalar C++, unsigned __int128 double-words, schoolbook + Barrett, g++ -O3)",
+            "cpu": model, "threads_all": threads,
+            "workload": "forward negacyclic NTT N=2^16, 124-bit q (the plain step's); vec_mulmod n=2^22, 124-bit",
+            "ntt_s_1core": round(ntt_1, 2), "ntt_s_all": round(ntt_all, 2),
+            "gmulmod_s_1core": round(mul_1 / 1e9, 4), "gmulmod_s_all": round(mul_all / 1e9, 4)}
 
 
 def main():
@@ -425,6 +469,13 @@ def main():
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(wl)
+        if "cpu_ref" in legs_on:
+            progress("cpu_ref (scalar C++ baseline)")
+            cr = cpu_ref_leg(wl)
+            cr["gpu_plain_over_1core"] = round(res["value"] / cr["ntt_s_1core"], 1)
+            if batched_ntt_s:
+                cr["gpu_batched_over_all"] = round(batched_ntt_s / cr["ntt_s_all"], 1)
+            res["cpu_ref"] = cr
     plan.destroy()
     print(json.dumps(res), flush=True)
 
