@@ -108,11 +108,19 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_calls(fn, stream, reps=20, warm=3):
-    """Mean microseconds per call of fn() on `stream` (HIP events)."""
+def time_calls(fn, stream, reps=20, warm=3, warm_s=0.03):
+    """Mean microseconds per call of fn() on `stream` (HIP events), after at
+    least `warm` calls and `warm_s` seconds of calls: the first calls of a
+    kernel after other work or idling ran up to 23% slower (252-bit
+    vec_mulmod at 2^23: 160.9 vs 130.7 us), which the steady state does not."""
     import torch
-    for _ in range(warm):
+    t0 = time.perf_counter()
+    done = 0
+    while done < warm or time.perf_counter() - t0 < warm_s:
         fn()
+        done += 1
+        if done % 8 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
