@@ -352,6 +352,11 @@ int res_fill(mw_server_s* S, const Req& R, ResEntry& E, uint64_t e) {
   E.b = (u64)R.r.in2;
   E.c = (u64)pool_ptr(S, R.out_off);
   const std::array<uint64_t, 3> key = {R.r.q[0], limbs == 2 ? R.r.q[1] : 0, limbs};
+  // a bounded memo: a stream of many distinct moduli starts it afresh
+  if (S->res.mod4.size() + S->res.mod2.size() > 4096) {
+    S->res.mod4.clear();
+    S->res.mod2.clear();
+  }
   if (limbs == 2) {
     auto it = S->res.mod4.find(key);
     if (it == S->res.mod4.end()) {
@@ -460,8 +465,10 @@ bool res_admit_head(mw_server_s* S) {
   const uint64_t e = X.published;
   const uint32_t slot = (uint32_t)(e & (kResRing - 1));
   if (X.broken) {
+    // fails without having taken memory: nothing to return to the pool
     S->queue.pop_front();
     R.state = RQ_RUNNING;
+    R.out_bytes = R.scratch_bytes = 0;
     complete(S, tk, R, true);
     S->cv_done.notify_all();
     return true;
