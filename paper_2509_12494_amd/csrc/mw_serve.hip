@@ -14,6 +14,13 @@
 // the batched executor, BLAS requests as their own kernels) on the slot's
 // stream.  Requests arriving meanwhile wait in the queue and go into the next
 // batch on the next free slot, so batches overlap on the device.
+//
+// With config.resident, one- and two-word requests of a few tiles instead go
+// to the device-resident request loop (mw_resident.h): the scheduler (or the
+// submitting thread, when the queue is empty) writes their descriptors into a
+// ring in mapped host memory, a persistent kernel runs them, and the
+// scheduler retires them by polling their done words there.  Both paths take
+// requests from the one queue in arrival order and share the memory pool.
 #include <hip/hip_runtime.h>
 #include <sys/prctl.h>
 
