@@ -310,8 +310,10 @@ typedef struct {
                              this many tiles (workgroup tasks: a BLAS tile is
                              1024 residues, a transform's tiles are the
                              batched executor's) go to the loop, the others
-                             keep the slot path; 0 = 16 (measured: past that
-                             the launched kernels are faster), at most 4096 */
+                             keep the slot path; 0 = every request the loop
+                             can take (4096 tiles).  A slot batch whose
+                             stream shares the loop's hardware queue waits
+                             until the loop yields (after 0.5 ms) */
 } mw_server_config;
 
 enum mw_request_op {
@@ -343,6 +345,8 @@ typedef struct {
   size_t pool_peak;             /* most budget bytes in use at once */
   uint64_t resident_requests;   /* requests run by the device-resident loop */
   uint64_t resident_launches;   /* launches of that loop */
+  uint64_t resident_yields;     /* times the loop was asked to yield to a slot
+                                   batch that waited behind it */
 } mw_server_stats;
 
 /* Creates the server on the current device (allocates the budget as one

@@ -36,6 +36,12 @@
 //    (marking the entry failed) after the wait bound.  The host relaunches
 //    the kernel when it publishes an entry and finds the kernel gone, and
 //    fails the entries an ended kernel took but did not complete.
+//  * Yielding: streams share the device's few hardware queues, and a kernel
+//    queued behind the loop on its queue cannot start before the loop ends.
+//    When work the host launched elsewhere stays unfinished too long, the
+//    host sets the yield word: the dispatcher takes no new entry, the loop
+//    ends once the entries it took are complete, whatever waited behind it
+//    runs, and the host launches the loop again after it.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -52,16 +58,19 @@ constexpr u32 kResMaxTiles = 4096;          // tiles per entry (12 bits of a til
 constexpr u32 kResLds = 48 * 1024;          // dynamic LDS of a worker: the largest tile it takes
 constexpr u32 kResBlasChunk = 4 * 256;      // residues per BLAS tile
 constexpr u32 kResMaxLog2N = 17;            // largest transform the loop takes (a plan's largest)
-// By default, requests of at most this many tiles go to the loop, larger
-// ones keep the slot path (mw_server_config.resident_max_tiles changes it).  Every tile pays an L2 invalidate and an L2 write-back on its
-// XCD, and the loop runs the run-time line engine, so past a few dozen tiles
-// the launched kernels (specialised tiles, no per-tile cache maintenance) are
-// faster.  Measured on MI355X, 20 K requests/s Poisson stream, p50 in us
-// (loop vs slot path): BLAS 2^10 (1 tile) 20.4 vs 23.7, 2^14 (16 tiles)
-// 25.2 vs 24.2, 2^16 (64) 32.7 vs 24.6; 124-bit NTT 2^10 (2 tiles) 29.3 vs
-// 33.7, 2^13 (16) 34.3 vs 36.0, 2^14 (32) 36.2 vs 36.8, 2^17 (256) 69.7 vs
-// 40.1.
-constexpr u32 kResRouteTiles = 16;
+// By default every request the loop can take goes to it; a smaller bound
+// (mw_server_config.resident_max_tiles) sends larger requests to the slot
+// path.  Per request class the loop is faster for small requests and slower
+// for large ones -- every tile pays an L2 invalidate and an L2 write-back on
+// its XCD, and the loop runs the run-time line engine (measured on MI355X,
+// 20 K requests/s Poisson stream, p50 in us, loop vs slot path: BLAS 2^10
+// (1 tile) 20.4 vs 23.7, 2^16 (64 tiles) 32.7 vs 24.6; 124-bit NTT 2^10
+// (2 tiles) 29.3 vs 33.7, 2^17 (256) 69.7 vs 40.1) -- but a slot-path
+// launch can land on the loop's hardware queue and then waits for the loop
+// to yield, so over the whole stream routing everything to the loop measured
+// best: p50 / p99 / mean 34.3 / 82.4 / 38.6 us against 37.9 / 91.8 / 40.3
+// for the slot path alone.
+constexpr u32 kResRouteTiles = kResMaxTiles;
 constexpr u64 kResTagMask = (u64(1) << 40) - 1;
 
 enum { RES_NTT = 0, RES_BLAS = 1 };
@@ -114,7 +123,8 @@ struct ResHost {
   u64 tail;                       // host: entries published
   u64 consumed;                   // device: entries the dispatcher has taken
   u32 stop;                       // host: leave once every entry is complete
-  u32 pad[3];
+  u32 yield;                      // host: take no new entry; leave once every one taken is complete
+  u32 pad[2];
   ResCtl ctl_init;                // staging of the control reset before a launch
   u64 done[kResRing];             // device: seq + 1 of the slot's last completed entry
   ResEntry ring[kResRing];

@@ -57,8 +57,10 @@ __device__ __forceinline__ void dispatch(const ResParams& p, u64& sh_a, u32& sh_
   for (;;) {
     if (t == 0) {
       store_agent(&D->ctl.beat, ++beat);
-      sh_a = load_system(&H->tail);
-      const u32 stop = load_system(&H->stop);
+      // while the host asks to yield, no new entry is taken
+      const u32 yielding = load_system(&H->yield);
+      sh_a = yielding ? consumed : load_system(&H->tail);
+      const u32 stop = load_system(&H->stop) | yielding;
       const u64 done = load_agent(&D->ctl.completed);
       const u64 now = wall_clock64();
       if (done != seen_done) {

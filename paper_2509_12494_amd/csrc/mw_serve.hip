@@ -55,6 +55,9 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr uint32_t kMaxBatch = 256;
 constexpr uint32_t kMaxTilesPerJob = 2048;
+// A slot batch still running this long after its launch makes the resident
+// loop yield (a slot batch of the serving mix takes tens of microseconds).
+constexpr double kYieldAfterUs = 500.0;
 
 double now_us() {
   using namespace std::chrono;
@@ -158,6 +161,7 @@ struct Slot {
   char* h_desc = nullptr;
   bool busy = false;
   double t_end = 0;              // dry run
+  double t_launch = 0;           // when its batch was launched
   std::vector<uint64_t> tickets;
 };
 
@@ -176,6 +180,7 @@ struct Resident {
   uint32_t route_tiles = kResRouteTiles;   // requests of at most this many tiles go to the loop
   uint64_t idle_ticks = 0, wait_ticks = 0, stall_ticks = 0;
   double last_query_us = 0;      // last check whether the loop has ended
+  bool yielding = false;         // the yield word is set
   uint64_t published = 0;        // entries published
   uint64_t gpub = 0;             // tiles published
   uint64_t tiles_out = 0;        // tiles of published entries not yet complete
@@ -434,6 +439,10 @@ bool res_ensure_running(mw_server_s* S, bool check_end) {
     // the loop has ended: an entry it took and did not complete never will
     res_retire(S);
     res_fail_live(S, start);
+    if (X.yielding) {
+      __atomic_store_n(&X.H->yield, 0u, __ATOMIC_RELEASE);
+      X.yielding = false;
+    }
     if (!untaken) return true;
   }
   const uint64_t gstart = start < X.published ? X.tile_start[start & (kResRing - 1)] : X.gpub;
@@ -566,6 +575,7 @@ bool admit_slot_batch(mw_server_s* S) {
   }
   if (batch.empty()) return false;   // the oldest request waits for memory
   slot->busy = true;
+  slot->t_launch = now_us();
   ++S->inflight;
   ++S->stats.batches;
   S->stats.max_batch_seen = std::max<uint64_t>(S->stats.max_batch_seen, batch.size());
@@ -626,6 +636,19 @@ void scheduler(mw_server_s* S) {
       slot.busy = false;
       --S->inflight;
       progress = true;
+    }
+    // a slot batch unfinished long after its launch may sit on the loop's
+    // hardware queue behind the loop: ask the loop to yield (its entries
+    // wait in the ring and the next launch takes them)
+    if (S->res.launched && !S->res.yielding && S->inflight) {
+      const double t = now_us();
+      for (const Slot& slot : S->slots)
+        if (slot.busy && t - slot.t_launch > kYieldAfterUs) {
+          __atomic_store_n(&S->res.H->yield, 1u, __ATOMIC_RELEASE);
+          S->res.yielding = true;
+          ++S->stats.resident_yields;
+          break;
+        }
     }
     if (!S->res.live.empty()) {
       if (res_retire(S)) progress = true;

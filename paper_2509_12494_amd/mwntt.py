@@ -70,7 +70,8 @@ class MwServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("max_batch_seen", ctypes.c_uint64), ("queue_peak", ctypes.c_uint64),
                 ("inflight_peak", ctypes.c_uint64), ("pool_peak", ctypes.c_size_t),
-                ("resident_requests", ctypes.c_uint64), ("resident_launches", ctypes.c_uint64)]
+                ("resident_requests", ctypes.c_uint64), ("resident_launches", ctypes.c_uint64),
+                ("resident_yields", ctypes.c_uint64)]
 
 
 class MwError(RuntimeError):

@@ -20,7 +20,7 @@ from .test_serve_gpu import _alone, _oracle_sample, _request, _workload
 pytestmark = pytest.mark.gpu
 
 BLAS_TILE = 1024       # residues per BLAS tile of the loop
-DEFAULT_TILES = 16     # the default routing bound
+DEFAULT_TILES = 4096   # the default routing bound: every request the loop can take
 
 
 def _tiles(it):
@@ -61,11 +61,11 @@ def _run_and_check(srv, items, serial, sample_every=3):
             assert [got[k] for k in ks] == _oracle_sample(it, ks), f"request {i}"
 
 
-@pytest.mark.parametrize("wide,max_tiles", [(False, 0), (True, 0), (False, 4096), (True, 4096)])
+@pytest.mark.parametrize("wide,max_tiles", [(False, 0), (True, 0), (False, 16), (True, 16)])
 def test_resident_burst_matches_alone(wide, max_tiles):
     """A burst of 56 requests (wide: a third of them 252-bit, which take the
-    slot path beside the loop; max_tiles 4096: every one- and two-word
-    request goes to the loop)."""
+    slot path beside the loop; max_tiles 16: requests of more tiles take the
+    slot path too)."""
     require_gpu()
     items, plans = _workload(56, seed=71 + wide, wide=wide, log2_range=(10, 15))
     srv = mwntt.MwServer(1 << 30, max_inflight=3, max_batch=16, resident=True, resident_max_tiles=max_tiles)
@@ -75,7 +75,7 @@ def test_resident_burst_matches_alone(wide, max_tiles):
     assert st["completed"] == len(items)
     expect = _in_loop(items, max_tiles)
     assert st["resident_requests"] == expect and st["resident_launches"] >= 1
-    if max_tiles == 0:
+    if max_tiles or wide:
         assert 0 < expect < len(items)      # both paths in use
     srv.destroy()
     for p in plans.values():
@@ -153,6 +153,28 @@ def test_resident_replay_poisson():
     assert len(lat) == len(items) and min(lat) > 0
     st = srv.stats()
     assert st["completed"] == len(items) and st["resident_requests"] == _in_loop(items, 0)
+    srv.destroy()
+    for p in plans.values():
+        p.destroy()
+
+
+def test_resident_slot_path_not_held_behind_the_loop():
+    """Requests routed to the slot path (more than 16 tiles) in an open-loop
+    replay of 4000 requests: a slot batch whose stream shares the loop's
+    hardware queue makes the loop yield after 0.5 ms, so no request waits
+    for the replay to end (before the yield, one waited the whole replay)."""
+    require_gpu()
+    import numpy as np
+    items, plans = _workload(4000, seed=17, log2_range=(10, 15))
+    g = np.random.Generator(np.random.PCG64(6))
+    gaps = g.exponential(1e6 / 20000.0, size=len(items))
+    arrivals = list(np.cumsum(gaps) - gaps[0])
+    srv = mwntt.MwServer(1 << 30, max_inflight=4, max_batch=64, resident=True, resident_max_tiles=16)
+    announce("resident yield", len(items))
+    lat, span = srv.replay([_request(it) for it in items], arrivals)
+    st = srv.stats()
+    assert st["completed"] == len(items) and 0 < st["resident_requests"] < len(items)
+    assert max(lat) < 100e3, (max(lat), st["resident_yields"])
     srv.destroy()
     for p in plans.values():
         p.destroy()
