@@ -304,6 +304,11 @@ typedef struct {
                              from a ring in mapped host memory and signals
                              completion there; the other requests, and all of
                              them in validate mode, keep the slot path.
+                             The loop holds one of the device's hardware
+                             queues while it runs: a kernel the caller
+                             launches on a stream that shares that queue
+                             starts only when the loop ends (20 ms after its
+                             last request, or at mw_server_destroy).
                              0: every request takes the slot path.  Ignored in
                              a dry run. */
   uint32_t resident_max_tiles; /* with resident: only requests of at most
