@@ -319,6 +319,10 @@ typedef struct {
                              can take (4096 tiles).  A slot batch whose
                              stream shares the loop's hardware queue waits
                              until the loop yields (after 0.5 ms) */
+  uint32_t resident_wait_us; /* with resident: how long a tile waits for the
+                             earlier phases of its request before giving up;
+                             a request with a tile that gave up completes as
+                             failed (mw_server_result: MW_EDEVICE).  0 = 2 s */
 } mw_server_config;
 
 enum mw_request_op {

@@ -756,7 +756,8 @@ int init_resident(mw_server_s* S) {
   X.grid = 2 * (uint32_t)cus;
   if (S->cfg.resident_max_tiles) X.route_tiles = S->cfg.resident_max_tiles;
   X.idle_ticks = (uint64_t)khz * 20;      // 20 ms
-  X.wait_ticks = (uint64_t)khz * 2000;    // 2 s
+  X.wait_ticks = S->cfg.resident_wait_us ? (uint64_t)khz * S->cfg.resident_wait_us / 1000
+                                         : (uint64_t)khz * 2000;   // 2 s
   X.stall_ticks = (uint64_t)khz * 5000;   // 5 s
   X.tile_start.assign(kResRing, 0);
   X.slot_ticket.assign(kResRing, 0);

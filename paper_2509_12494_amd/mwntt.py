@@ -63,7 +63,8 @@ class MwRequest(ctypes.Structure):
 class MwServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("dry_run", ctypes.c_uint32), ("spin_us", ctypes.c_uint32),
-                ("resident", ctypes.c_uint32), ("resident_max_tiles", ctypes.c_uint32)]
+                ("resident", ctypes.c_uint32), ("resident_max_tiles", ctypes.c_uint32),
+                ("resident_wait_us", ctypes.c_uint32)]
 
 
 class MwServerStats(ctypes.Structure):
@@ -421,9 +422,10 @@ class MwServer:
     """Owning wrapper of an mw_server_t (continuous batching of NTT / BLAS requests)."""
 
     def __init__(self, hbm_budget: int, max_inflight: int = 4, max_batch: int = 64, dry_run: bool = False,
-                 spin_us: int = 0, resident: bool = False, resident_max_tiles: int = 0):
+                 spin_us: int = 0, resident: bool = False, resident_max_tiles: int = 0,
+                 resident_wait_us: int = 0):
         cfg = MwServerConfig(hbm_budget, max_inflight, max_batch, 1 if dry_run else 0, spin_us,
-                             1 if resident else 0, resident_max_tiles)
+                             1 if resident else 0, resident_max_tiles, resident_wait_us)
         h = ctypes.c_void_p()
         _check(lib().mw_server_create(ctypes.byref(h), ctypes.byref(cfg)), "mw_server_create")
         self._h = h

@@ -180,6 +180,42 @@ def test_resident_slot_path_not_held_behind_the_loop():
         p.destroy()
 
 
+def test_resident_dependency_wait_bound_fails_requests_cleanly():
+    """A tile's wait for the earlier phases of its request bounded at 1 us
+    (forced from the host): tiles of two-phase 2^16 transforms give up, their
+    requests complete as failed (MW_EDEVICE) instead of hanging, every request
+    that did not fail is exact, the loop ends normally, and a server with the
+    default bound afterwards is exact again."""
+    require_gpu()
+    import torch
+    items, plans = _workload(12, seed=103, log2_range=(16, 16), widths=[124])
+    items = [it for it in items if it["plan"] is not None]
+    srv = mwntt.MwServer(1 << 30, max_inflight=2, max_batch=8, resident=True, resident_wait_us=1)
+    announce("resident wait bound", len(items))
+    tickets = [srv.submit(_request(it)) for it in items]
+    failed = 0
+    for i, (t, it) in enumerate(zip(tickets, items)):
+        try:
+            ptr, _ = srv.result(t, wait=True)
+        except mwntt.MwError as e:
+            assert e.status == -5, e          # MW_EDEVICE
+            failed += 1
+            srv.release(t)
+            continue
+        out = mwntt.copy_to_tensor(ptr, it["a"])
+        torch.cuda.synchronize()
+        srv.release(t)
+        assert torch.equal(out, _alone(it)), f"request {i}"
+    assert failed >= 1
+    assert srv.stats()["completed"] == len(items)
+    srv.destroy()
+    srv = mwntt.MwServer(1 << 30, max_inflight=2, max_batch=8, resident=True)
+    _run_and_check(srv, items[:4], serial=False, sample_every=4)
+    srv.destroy()
+    for p in plans.values():
+        p.destroy()
+
+
 def test_resident_validate_mode_keeps_slot_path():
     """In validate mode every request takes the slot path (its inputs are
     checked on a slot's stream)."""
