@@ -277,8 +277,8 @@ int ntt_batch_destroy(ntt_batch_t batch);
 /* free, and batches overlap on the device.  Completion is detected from    */
 /* stream events; latency is completion minus submission.  Admission is     */
 /* first-in first-out: a request that does not fit blocks the ones behind   */
-/* it until memory is released.  With `resident` set, small requests run   */
-/* in a device-resident loop instead (see mw_server_config.resident).       */
+/* it until memory is released.  With `resident` set, one- and two-word    */
+/* requests run in a device-resident loop instead (mw_server_config).      */
 /* ------------------------------------------------------------------------ */
 typedef struct mw_server_s* mw_server_t;
 
