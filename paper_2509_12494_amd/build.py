@@ -36,10 +36,18 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+# Host-only sanitizer instrumentation (device code untouched): the flags go to
+# the host pass of every compile and to the link.
+SANITIZE = {
+    "address": ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"],
+    "undefined": ["-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-fno-sanitize-recover=undefined"],
+}
+
+
+def _compile(src, verbose, build_dir=BUILD_DIR, san=()):
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
     extra = ILP_FLAGS if src in ILP_SOURCES else []
-    cmd = [HIPCC] + COMMON + HIP_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + COMMON + HIP_FLAGS + extra + list(san) + ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -70,21 +78,30 @@ def build_pycall(verbose: bool = False) -> str:
     return PYCALL
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, sanitize: str = "") -> str:
+    """Builds the library; with sanitize ("address" or "undefined") a
+    host-instrumented copy under _build/sanitize-<kind>/ instead, for running
+    the host code's tests with the sanitizer runtime preloaded (the library
+    is then selected with MWNTT_LIB)."""
+    san = SANITIZE[sanitize] if sanitize else []
+    build_dir = os.path.join(BUILD_DIR, "sanitize-" + sanitize) if sanitize else BUILD_DIR
+    out = os.path.join(build_dir, "libmwntt.so") if sanitize else LIB
+    os.makedirs(build_dir, exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+        objs = list(ex.map(lambda s: _compile(s, verbose, build_dir, san), SOURCES))
+    tmp = out + ".tmp"
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + san + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
-    os.replace(tmp, LIB)
-    build_pycall(verbose)
-    return LIB
+    os.replace(tmp, out)
+    if not sanitize:
+        build_pycall(verbose)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    kind = sys.argv[sys.argv.index("--sanitize") + 1] if "--sanitize" in sys.argv else ""
+    print(build(verbose="-v" in sys.argv, sanitize=kind))

@@ -17,7 +17,9 @@ import os
 from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmwntt.so")
+# MWNTT_LIB loads another build of the library instead (the host-sanitizer
+# builds of `python -m paper_2509_12494_amd.build --sanitize ...`).
+LIB_PATH = os.environ.get("MWNTT_LIB") or os.path.join(HERE, "libmwntt.so")
 
 MW_OK = 0
 NTT_BITREV_OUT = 0x1
