@@ -466,8 +466,7 @@ int cpuref_plan_create(void** plan, uint32_t log2n, const uint64_t* q, uint32_t 
 int cpuref_plan_root(void* plan, uint64_t* psi) {
   PlanAny* A = static_cast<PlanAny*>(plan);
   if (!A || !psi) return CR_EINVAL;
-  // fwd[1] = psi^bitrev(1) = psi^(N/2): recover psi from the natural powers
-  // instead: psi = fwd[bitrev^-1(1)], i.e. the entry at index bitrev(1)
+  // fwd[i] = psi^bitrev(i), so psi itself sits at index bitrev(1)
   if (A->limbs == 1) {
     const Plan<1>& P = *static_cast<Plan<1>*>(A->p);
     memcpy(psi, P.fwd[bitrev(1, P.log2n)].w, 8);
