@@ -11,9 +11,11 @@ torch's current stream.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import functools
 import os
+import weakref
 from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -420,6 +422,20 @@ def make_request(op: int, inp, inp2=None, plan: Optional[NttPlan] = None, q: int
     return r
 
 
+# Servers still alive when the interpreter exits are destroyed first: each
+# owns a scheduler thread and possibly a running resident loop.
+_live_servers: "weakref.WeakSet[MwServer]" = weakref.WeakSet()
+
+
+@atexit.register
+def _destroy_live_servers() -> None:
+    for srv in list(_live_servers):
+        try:
+            srv.destroy()
+        except Exception:
+            pass
+
+
 class MwServer:
     """Owning wrapper of an mw_server_t (continuous batching of NTT / BLAS requests)."""
 
@@ -432,6 +448,7 @@ class MwServer:
         _check(lib().mw_server_create(ctypes.byref(h), ctypes.byref(cfg)), "mw_server_create")
         self._h = h
         self._keep = {}
+        _live_servers.add(self)
 
     def submit(self, req: MwRequest, keep=None) -> int:
         t = ctypes.c_uint64()
