@@ -6,6 +6,8 @@
 // chunks of element-wise operations.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "mw_exec_tiles.h"
 #include "mw_resident.h"
 
@@ -14,6 +16,9 @@ namespace mw {
 namespace {
 
 constexpr u32 kEntryUnits = sizeof(ResEntry) / 16;
+// the 16-byte unit of a descriptor whose first word is its tile count
+constexpr u32 kTotalUnit = offsetof(ResEntry, total) / 16;
+static_assert(offsetof(ResEntry, total) % 16 == 0, "the tile count starts a 16-byte unit");
 
 __device__ __forceinline__ void fence_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ __forceinline__ void fence_release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
@@ -82,17 +87,28 @@ __device__ __forceinline__ void dispatch(const ResParams& p, u64& sh_a, u32& sh_
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
       for (; consumed < tail; ++consumed) {
         const u32 slot = (u32)(consumed & (kResRing - 1));
-        copy_entry(&D->dent[slot], &H->ring[slot]);
-        const u32 total = load_system(&H->ring[slot].total);   // a vector load, never the scalar cache
+        {
+          // one PCIe round trip: each lane moves 16-byte units, and the lane
+          // holding the unit with the tile count passes it on through LDS
+          const uint4* src = reinterpret_cast<const uint4*>(&H->ring[slot]);
+          uint4* dst = reinterpret_cast<uint4*>(&D->dent[slot]);
+          for (u32 k = t; k < kEntryUnits; k += blockDim.x) {
+            const uint4 u = src[k];
+            dst[k] = u;
+            if (k == kTotalUnit) sh_b = u.x;
+          }
+        }
         // the descriptor is visible at agent scope before any tile word of it
         wait_own_stores();
         __syncthreads();
+        const u32 total = sh_b;
         fence_release_agent();
         for (u32 i = t; i < total; i += blockDim.x) {
           const u64 g = gpub + i;
           store_agent(&D->tiles[g & (kResTileRing - 1)], ((g & kResTagMask) << 24) | ((u64)slot << 12) | i);
         }
         gpub += total;
+        __syncthreads();   // every lane has read the count before the next entry's is written
       }
       if (t == 0) {
         __hip_atomic_store(&H->consumed, consumed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
