@@ -146,10 +146,12 @@ def time_graph(fn, stream, reps=20):
     return us
 
 
-def serving_leg(count, rate=20000.0, budget=1 << 30, spin_us=0, modes=("slots", "resident")):
+def serving_leg(count, rate=20000.0, budget=1 << 30, spin_us=0, modes=("slots", "resident", "resident_spin")):
     """Open-loop Poisson stream through the serving runtime (inputs pre-staged),
     once per scheduling mode: "slots" (the host scheduler launches each batch
-    on a stream) and "resident" (the device-resident request loop).
+    on a stream), "resident" (the device-resident request loop) and
+    "resident_spin" (the loop with a scheduler that polls without sleeping,
+    spin_us = 1000: one busy host core).
 
     70% transforms (half forward, half inverse) with N = 2^e, e uniform in
     10..17; 30% BLAS (half mulmod, half axpymod) with length floor(2^u), u
@@ -185,7 +187,8 @@ def serving_leg(count, rate=20000.0, budget=1 << 30, spin_us=0, modes=("slots", 
     progress(f"serving: {len(plans)} plans, {len(bufs)} input buffers staged")
     out = {"requests": count, "offered_rate": rate, "hbm_budget": budget, "spin_us": spin_us}
     for mode in modes:
-        srv = mwntt.MwServer(budget, max_inflight=4, max_batch=64, spin_us=spin_us, resident=mode == "resident")
+        srv = mwntt.MwServer(budget, max_inflight=4, max_batch=64, spin_us=1000 if mode == "resident_spin" else spin_us,
+                             resident=mode.startswith("resident"))
         warm = min(2000, count)
         srv.replay(reqs[:warm], [a - arrivals[0] for a in arrivals[:warm]])
         lat, span = srv.replay(reqs, arrivals)
