@@ -272,8 +272,9 @@ def cpu_ref_leg(wl, budget_s=1.5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=2000,
+                    help="untimed steps before the timed ones (2000 steps, about 60 ms: the clocks settle)")
     ap.add_argument("--batch", type=int, default=96, help="transforms per call in the batched leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=100000,
