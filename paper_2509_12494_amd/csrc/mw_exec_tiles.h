@@ -21,8 +21,9 @@ constexpr u32 kFixedLogLMin = 5, kFixedLogLMax = 9;
 // length has compile-time code runs the tile code of the single-purpose
 // kernels (stage loops unrolled, indices constant); any other tile the
 // run-time line engine.
-template <int W, int LOGP, int DIR, int MODE, bool FIXED>
+template <int W, int LOGP, int DIR, int MODE, bool FIXED, class IO = CachedIO>
 __device__ __forceinline__ void run_tile(const NttParams<W>& p, Res<W>* lds, u32 tile) {
+  static_assert(!FIXED || std::is_same_v<IO, CachedIO>, "the compile-time tiles use cached accesses");
   if constexpr (FIXED) {
     const u32 logl = MODE == MODE_COL ? p.log_n1 : p.log_n - p.log_n1;
     if (logl >= kFixedLogLMin && logl <= kFixedLogLMax && (p.lines << (logl - LOGP)) == kExecThreads) {
@@ -35,7 +36,7 @@ __device__ __forceinline__ void run_tile(const NttParams<W>& p, Res<W>* lds, u32
       }
     }
   }
-  rt_tile<W, LOGP, DIR, MODE>(p, lds, tile);
+  rt_tile<W, LOGP, DIR, MODE, IO>(p, lds, tile);
 }
 
 // Fused row tile of a product with the line length fixed at compile time and
@@ -98,9 +99,10 @@ __device__ __forceinline__ void fixed_fused_row(const NttParams<W>& pf, const Nt
 // workgroup, the compile-time version -- for two-word moduli only: with the
 // one- and four-word kernels' other tiles it exceeds their registers and
 // spills.
-template <int W, int LOGP, bool FIXED>
+template <int W, int LOGP, bool FIXED, class IO = CachedIO>
 __device__ __forceinline__ void run_fused_row(const NttParams<W>& pf, const NttParams<W>& pi, const Res<W>* src2,
                                               Res<W>* lds, u32 tile) {
+  static_assert(!FIXED || std::is_same_v<IO, CachedIO>, "the compile-time tiles use cached accesses");
   if constexpr (FIXED && W == 4) {
     const u32 logl = pf.log_n - pf.log_n1;
     if (logl >= kFixedLogLMin && logl <= kFixedLogLMax && (pf.lines << (logl - LOGP)) == kExecThreads) {
@@ -113,10 +115,10 @@ __device__ __forceinline__ void run_fused_row(const NttParams<W>& pf, const NttP
       }
     }
   }
-  rt_fused_row<W, LOGP>(pf, pi, src2, lds, tile);
+  rt_fused_row<W, LOGP, IO>(pf, pi, src2, lds, tile);
 }
 
-template <int W, int LOGP, bool FIXED>
+template <int W, int LOGP, bool FIXED, class IO = CachedIO>
 __device__ __forceinline__ void run_item(const JobDesc& J, const ModConst<W>& mc, u32 phase, u32 tile,
                                          unsigned char* smem) {
   NttParams<W> p;
@@ -139,19 +141,19 @@ __device__ __forceinline__ void run_item(const JobDesc& J, const ModConst<W>& mc
     p.tw = twf;
     if (phase == 0) {
       p.src = in; p.dst = scr; p.lines = J.lines_col;
-      run_tile<W, LOGP, DIR_FWD, MODE_COL, FIXED>(p, lds, tile);
+      run_tile<W, LOGP, DIR_FWD, MODE_COL, FIXED, IO>(p, lds, tile);
     } else {
       p.src = scr; p.dst = out; p.lines = J.lines_row; p.permute = J.perm_out;
-      run_tile<W, LOGP, DIR_FWD, MODE_ROW, FIXED>(p, lds, tile);
+      run_tile<W, LOGP, DIR_FWD, MODE_ROW, FIXED, IO>(p, lds, tile);
     }
   } else if (J.op == JOB_INV) {
     p.tw = twi;
     if (phase == 0) {
       p.src = in; p.dst = scr; p.lines = J.lines_row; p.permute = J.perm_in;
-      run_tile<W, LOGP, DIR_INV, MODE_ROW, FIXED>(p, lds, tile);
+      run_tile<W, LOGP, DIR_INV, MODE_ROW, FIXED, IO>(p, lds, tile);
     } else {
       p.src = scr; p.dst = out; p.lines = J.lines_col;
-      run_tile<W, LOGP, DIR_INV, MODE_COL, FIXED>(p, lds, tile);
+      run_tile<W, LOGP, DIR_INV, MODE_COL, FIXED, IO>(p, lds, tile);
     }
   } else {
     const u32 ncol = J.tiles[2];
@@ -160,15 +162,15 @@ __device__ __forceinline__ void run_item(const JobDesc& J, const ModConst<W>& mc
       const bool second = tile >= ncol;
       p.src = second ? in2 : in;
       p.dst = second ? scr + N : scr;
-      run_tile<W, LOGP, DIR_FWD, MODE_COL, FIXED>(p, lds, second ? tile - ncol : tile);
+      run_tile<W, LOGP, DIR_FWD, MODE_COL, FIXED, IO>(p, lds, second ? tile - ncol : tile);
     } else if (phase == 1) {
       NttParams<W> pi = p;
       p.tw = twf; p.lines = J.lines_row; p.src = scr; p.dst = scr;
       pi.tw = twi; pi.lines = J.lines_row;
-      run_fused_row<W, LOGP, FIXED>(p, pi, scr + N, lds, tile);
+      run_fused_row<W, LOGP, FIXED, IO>(p, pi, scr + N, lds, tile);
     } else {
       p.tw = twi; p.lines = J.lines_col; p.src = scr; p.dst = out;
-      run_tile<W, LOGP, DIR_INV, MODE_COL, FIXED>(p, lds, tile);
+      run_tile<W, LOGP, DIR_INV, MODE_COL, FIXED, IO>(p, lds, tile);
     }
   }
 }

@@ -30,7 +30,7 @@ __device__ __forceinline__ u32 rt_npad(u32 logl, u32 logp) {
 // LAST_INV: the round may hold the final inverse stage (stage 0, N^-1 folded
 // in); CANON: make the outputs canonical.  Both are known where a round is
 // called, so rounds without them carry no code for them.
-template <int W, int LOGP, int NP, int DIR, bool LAST_INV, bool CANON>
+template <int W, int LOGP, int NP, int DIR, bool LAST_INV, bool CANON, class IO = CachedIO>
 __device__ __forceinline__ void rt_round(Res<W>* line, bool active, u32 logl, u32 s0, u32 tid, u32 base,
                                          const Tw<W>* __restrict__ tw, const NttParams<W>& p) {
   constexpr int P = 1 << LOGP;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void rt_round(Res<W>* line, bool active, u32 logl, u3
             gs_bfly_last(x[u], x[u | (1 << ib)], p.ninv, p.ninv_w1, p.M);
           }
         } else {
-          const Tw<W> t = load_tw(tw, (base << s) + g);
+          const Tw<W> t = IO::tw(tw, (base << s) + g);
 #pragma unroll
           for (int lo = 0; lo < (1 << ib); ++lo) {
             const int u = (gi << (ib + 1)) | lo;
@@ -77,52 +77,52 @@ __device__ __forceinline__ void rt_round(Res<W>* line, bool active, u32 logl, u3
   __syncthreads();
 }
 
-template <int W, int LOGP, int DIR, bool LAST_INV, bool CANON>
+template <int W, int LOGP, int DIR, bool LAST_INV, bool CANON, class IO = CachedIO>
 __device__ __forceinline__ void rt_first_round(u32 p0, Res<W>* line, bool active, u32 logl, u32 tid, u32 base,
                                                const Tw<W>* __restrict__ tw, const NttParams<W>& p) {
   // p0 in [1, LOGP]: stages 0 .. p0-1 of the line
   if constexpr (LOGP >= 1) {
-    if (p0 == 1) { rt_round<W, LOGP, 1, DIR, LAST_INV, CANON>(line, active, logl, 0, tid, base, tw, p); return; }
+    if (p0 == 1) { rt_round<W, LOGP, 1, DIR, LAST_INV, CANON, IO>(line, active, logl, 0, tid, base, tw, p); return; }
   }
   if constexpr (LOGP >= 2) {
-    if (p0 == 2) { rt_round<W, LOGP, 2, DIR, LAST_INV, CANON>(line, active, logl, 0, tid, base, tw, p); return; }
+    if (p0 == 2) { rt_round<W, LOGP, 2, DIR, LAST_INV, CANON, IO>(line, active, logl, 0, tid, base, tw, p); return; }
   }
   if constexpr (LOGP >= 3) {
-    if (p0 == 3) { rt_round<W, LOGP, 3, DIR, LAST_INV, CANON>(line, active, logl, 0, tid, base, tw, p); return; }
+    if (p0 == 3) { rt_round<W, LOGP, 3, DIR, LAST_INV, CANON, IO>(line, active, logl, 0, tid, base, tw, p); return; }
   }
   if constexpr (LOGP >= 4) {
-    rt_round<W, LOGP, 4, DIR, LAST_INV, CANON>(line, active, logl, 0, tid, base, tw, p);
+    rt_round<W, LOGP, 4, DIR, LAST_INV, CANON, IO>(line, active, logl, 0, tid, base, tw, p);
   }
 }
 
 // All stages of a line of 2^logl points (logl >= LOGP) held in LDS.
 // LAST_INV: the line holds the final inverse stage; FINAL_FWD: canonicalize
 // after the last forward stage.
-template <int W, int LOGP, int DIR, bool LAST_INV, bool FINAL_FWD>
+template <int W, int LOGP, int DIR, bool LAST_INV, bool FINAL_FWD, class IO = CachedIO>
 __device__ __forceinline__ void rt_line_stages(Res<W>* line, bool active, u32 logl, u32 tid, u32 base,
                                                const Tw<W>* __restrict__ tw, const NttParams<W>& p) {
   const u32 R = (logl + LOGP - 1) / LOGP;
   const u32 p0 = logl - LOGP * (R - 1);
   if (DIR == DIR_FWD) {
     if (R == 1) {
-      rt_first_round<W, LOGP, DIR, false, FINAL_FWD>(p0, line, active, logl, tid, base, tw, p);
+      rt_first_round<W, LOGP, DIR, false, FINAL_FWD, IO>(p0, line, active, logl, tid, base, tw, p);
       return;
     }
-    rt_first_round<W, LOGP, DIR, false, false>(p0, line, active, logl, tid, base, tw, p);
+    rt_first_round<W, LOGP, DIR, false, false, IO>(p0, line, active, logl, tid, base, tw, p);
     for (u32 r = 1; r + 1 < R; ++r)
-      rt_round<W, LOGP, LOGP, DIR, false, false>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p);
-    rt_round<W, LOGP, LOGP, DIR, false, FINAL_FWD>(line, active, logl, p0 + (R - 2) * LOGP, tid, base, tw, p);
+      rt_round<W, LOGP, LOGP, DIR, false, false, IO>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p);
+    rt_round<W, LOGP, LOGP, DIR, false, FINAL_FWD, IO>(line, active, logl, p0 + (R - 2) * LOGP, tid, base, tw, p);
   } else {
     // only the first round holds stage 0
     for (u32 r = R - 1; r >= 1; --r)
-      rt_round<W, LOGP, LOGP, DIR, false, false>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p);
-    rt_first_round<W, LOGP, DIR, LAST_INV, false>(p0, line, active, logl, tid, base, tw, p);
+      rt_round<W, LOGP, LOGP, DIR, false, false, IO>(line, active, logl, p0 + (r - 1) * LOGP, tid, base, tw, p);
+    rt_first_round<W, LOGP, DIR, LAST_INV, false, IO>(p0, line, active, logl, tid, base, tw, p);
   }
 }
 
 // One column or row tile of a single transform (batch index 0 of p.src /
 // p.dst), with run-time line length.  `tile` indexes the tiles of the pass.
-template <int W, int LOGP, int DIR, int MODE>
+template <int W, int LOGP, int DIR, int MODE, class IO = CachedIO>
 __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 tile) {
   static_assert(MODE == MODE_COL || MODE == MODE_ROW, "two-pass tiles only");
   const u32 log_n = p.log_n, log_n1 = p.log_n1, log_n2 = log_n - log_n1;
@@ -151,7 +151,7 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
     const u64 N2 = (u64)1 << log_n2;
     copy_staged<W, P>(
         t, nthreads, in_tile,
-        [&](u32 e) { return ResIO<W>::load(p.src + (e >> log_lines) * N2 + c0 + (e & (lines - 1))); },
+        [&](u32 e) { return IO::load(p.src + (e >> log_lines) * N2 + c0 + (e & (lines - 1))); },
         [&](u32 e, const Res<W>& v) { lds[(e & (lines - 1)) * npad + rt_pad<LOGP>(e >> log_lines, logl)] = v; });
   } else {
     const u32 n1_over_g = (1u << log_n1) >> log_lines;
@@ -159,7 +159,7 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
       const u32 col = brev(b_lo, log_n1 - log_lines) << log_lines;
       copy_staged<W, P>(
           t, nthreads, in_tile,
-          [&](u32 e) { return ResIO<W>::load(p.src + ((u64)(e >> log_lines) << log_n1) + col + (e & (lines - 1))); },
+          [&](u32 e) { return IO::load(p.src + ((u64)(e >> log_lines) << log_n1) + col + (e & (lines - 1))); },
           [&](u32 e, const Res<W>& v) {
             lds[brev(e & (lines - 1), log_lines) * npad + rt_pad<LOGP>(brev(e >> log_lines, logl), logl)] = v;
           });
@@ -168,7 +168,7 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
           t, nthreads, in_tile,
           [&](u32 e) {
             const u32 b = (e >> logl) * n1_over_g + b_lo;
-            return ResIO<W>::load(p.src + ((u64)b << logl) + (e & (L - 1)));
+            return IO::load(p.src + ((u64)b << logl) + (e & (L - 1)));
           },
           [&](u32 e, const Res<W>& v) { lds[(e >> logl) * npad + rt_pad<LOGP>(e & (L - 1), logl)] = v; });
     }
@@ -177,7 +177,7 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
 
   u32 base = 1;
   if (MODE == MODE_ROW) base = (1u << log_n1) + line_id * ((1u << log_n1) >> log_lines) + b_lo;
-  rt_line_stages<W, LOGP, DIR, DIR == DIR_INV && MODE != MODE_ROW, DIR == DIR_FWD && MODE != MODE_COL>(
+  rt_line_stages<W, LOGP, DIR, DIR == DIR_INV && MODE != MODE_ROW, DIR == DIR_FWD && MODE != MODE_COL, IO>(
       lds + line_id * npad, active, logl, lane, base, p.tw, p);
 
   // ---- LDS -> device memory ----
@@ -186,7 +186,7 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
     copy_staged<W, P>(
         t, nthreads, in_tile,
         [&](u32 e) { return lds[(e & (lines - 1)) * npad + rt_pad<LOGP>(e >> log_lines, logl)]; },
-        [&](u32 e, const Res<W>& v) { ResIO<W>::store(p.dst + (e >> log_lines) * N2 + c0 + (e & (lines - 1)), v); });
+        [&](u32 e, const Res<W>& v) { IO::store(p.dst + (e >> log_lines) * N2 + c0 + (e & (lines - 1)), v); });
   } else {
     const u32 n1_over_g = (1u << log_n1) >> log_lines;
     if (DIR == DIR_FWD && p.permute) {
@@ -197,14 +197,14 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
             return lds[brev(e & (lines - 1), log_lines) * npad + rt_pad<LOGP>(brev(e >> log_lines, logl), logl)];
           },
           [&](u32 e, const Res<W>& v) {
-            ResIO<W>::store(p.dst + ((u64)(e >> log_lines) << log_n1) + col + (e & (lines - 1)), v);
+            IO::store(p.dst + ((u64)(e >> log_lines) << log_n1) + col + (e & (lines - 1)), v);
           });
     } else {
       copy_staged<W, P>(
           t, nthreads, in_tile, [&](u32 e) { return lds[(e >> logl) * npad + rt_pad<LOGP>(e & (L - 1), logl)]; },
           [&](u32 e, const Res<W>& v) {
             const u32 b = (e >> logl) * n1_over_g + b_lo;
-            ResIO<W>::store(p.dst + ((u64)b << logl) + (e & (L - 1)), v);
+            IO::store(p.dst + ((u64)b << logl) + (e & (L - 1)), v);
           });
     }
   }
@@ -216,7 +216,7 @@ __device__ __forceinline__ void rt_tile(const NttParams<W>& p, Res<W>* lds, u32 
 // back over a's rows.  Everything stays in bit-reversed order, which is the
 // order the inverse's row pass takes, so no permutation is needed.  `lds`
 // holds 2 * lines * npad residues.  `pi` carries the inverse table and N^-1.
-template <int W, int LOGP>
+template <int W, int LOGP, class IO = CachedIO>
 __device__ __forceinline__ void rt_fused_row(const NttParams<W>& pf, const NttParams<W>& pi, const Res<W>* src2,
                                              Res<W>* lds, u32 tile) {
   const u32 log_n = pf.log_n, log_n1 = pf.log_n1, log_n2 = log_n - log_n1;
@@ -247,8 +247,8 @@ __device__ __forceinline__ void rt_fused_row(const NttParams<W>& pf, const NttPa
     for (int k = 0; k < P; ++k) {
       const u32 e = t + (u32)k * nthreads;
       if (in_tile(e)) {
-        va[k] = ResIO<W>::load(pf.src + off(e));
-        vb[k] = ResIO<W>::load(src2 + off(e));
+        va[k] = IO::load(pf.src + off(e));
+        vb[k] = IO::load(src2 + off(e));
       }
     }
 #pragma unroll
@@ -262,8 +262,8 @@ __device__ __forceinline__ void rt_fused_row(const NttParams<W>& pf, const NttPa
   }
   __syncthreads();
   const u32 base = (1u << log_n1) + row0 + line_id;
-  rt_line_stages<W, LOGP, DIR_FWD, false, true>(la + line_id * npad, active, logl, lane, base, pf.tw, pf);
-  rt_line_stages<W, LOGP, DIR_FWD, false, true>(lb + line_id * npad, active, logl, lane, base, pf.tw, pf);
+  rt_line_stages<W, LOGP, DIR_FWD, false, true, IO>(la + line_id * npad, active, logl, lane, base, pf.tw, pf);
+  rt_line_stages<W, LOGP, DIR_FWD, false, true, IO>(lb + line_id * npad, active, logl, lane, base, pf.tw, pf);
   // point-wise Barrett products; the scaled or plain form is chosen once for
   // the loop (a uniform branch on the job's modulus)
   const auto pointwise = [&](auto norm) {
@@ -276,10 +276,10 @@ __device__ __forceinline__ void rt_fused_row(const NttParams<W>& pf, const NttPa
   if (pf.M.shift) pointwise(std::true_type{});
   else pointwise(std::false_type{});
   __syncthreads();
-  rt_line_stages<W, LOGP, DIR_INV, false, false>(la + line_id * npad, active, logl, lane, base, pi.tw, pi);
+  rt_line_stages<W, LOGP, DIR_INV, false, false, IO>(la + line_id * npad, active, logl, lane, base, pi.tw, pi);
   copy_staged<W, P>(
       t, nthreads, in_tile, [&](u32 e) { return la[slot(e)]; },
-      [&](u32 e, const Res<W>& v) { ResIO<W>::store(pf.dst + off(e), v); });
+      [&](u32 e, const Res<W>& v) { IO::store(pf.dst + off(e), v); });
 }
 
 }  // namespace mw

@@ -70,6 +70,57 @@ __device__ __forceinline__ Tw<W> load_tw(const Tw<W>* t, u32 idx) {
   return r;
 }
 
+// Device-memory access of the run-time tile bodies (mw_ntt_rt.h), as a
+// template policy: load and store move the residues a tile transforms, tw
+// reads its twiddle table.
+//
+// CachedIO: ordinary loads and stores through the compute unit's L1 and the
+// XCD's L2, for kernels whose workgroups exchange data only across launches.
+//
+// LoopIO, for the persistent request loop, where a tile reads what tiles on
+// other XCDs wrote in the same launch: residues move as relaxed device-scope
+// atomics on 64-bit words.  Such a load does not return a line the L1 or the
+// XCD's L2 holds from before another XCD's write, and such a store is written
+// through to memory, so that once the writing wave has waited for its stores
+// they are visible to every XCD: neither side needs an L2 invalidate or
+// write-back for them.  Twiddle tables, which no tile writes, are read
+// through the caches.
+struct CachedIO {
+  template <int W>
+  __device__ static __forceinline__ Res<W> load(const Res<W>* p) { return ResIO<W>::load(p); }
+  template <int W>
+  __device__ static __forceinline__ void store(Res<W>* p, const Res<W>& v) { ResIO<W>::store(p, v); }
+  template <int W>
+  __device__ static __forceinline__ Tw<W> tw(const Tw<W>* t, u32 idx) { return load_tw(t, idx); }
+};
+
+struct LoopIO {
+  template <int W>
+  __device__ static __forceinline__ Res<W> load(const Res<W>* p) {
+    static_assert(W % 2 == 0, "whole 64-bit words");
+    u64* s = reinterpret_cast<u64*>(const_cast<Res<W>*>(p));
+    Res<W> r;
+#pragma unroll
+    for (int k = 0; k < W / 2; ++k) {
+      const u64 x = __hip_atomic_load(s + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      r.v[2 * k] = (u32)x;
+      r.v[2 * k + 1] = (u32)(x >> 32);
+    }
+    return r;
+  }
+  template <int W>
+  __device__ static __forceinline__ void store(Res<W>* p, const Res<W>& v) {
+    static_assert(W % 2 == 0, "whole 64-bit words");
+    u64* d = reinterpret_cast<u64*>(p);
+#pragma unroll
+    for (int k = 0; k < W / 2; ++k)
+      __hip_atomic_store(d + k, (u64)v.v[2 * k] | ((u64)v.v[2 * k + 1] << 32), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+  template <int W>
+  __device__ static __forceinline__ Tw<W> tw(const Tw<W>* t, u32 idx) { return load_tw(t, idx); }
+};
+
 enum { DIR_FWD = 0, DIR_INV = 1 };
 enum { MODE_FULL = 0, MODE_COL = 1, MODE_ROW = 2 };
 

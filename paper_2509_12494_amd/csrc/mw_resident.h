@@ -10,23 +10,28 @@
 //    entry it copies the descriptor into device memory and writes one word
 //    per tile into the tile ring: word g (global tile number) is
 //    g << 24 | slot << 12 | tile, stored at g mod kResTileRing.
-//  * Every other workgroup (a worker) claims the next global tile number g
-//    with an atomic add, waits until word g carries tag g, then runs that
-//    tile.  A tile of phase k > 0 first waits until the entry's completed-tile
-//    count covers every tile of the earlier phases (tiles are numbered phase
-//    by phase, so the earliest unfinished tile never waits on a later one and
-//    the loop cannot deadlock).  The workgroup that completes the entry's last
-//    tile stores seq + 1 (bit 63: a dependency wait timed out) into the
-//    slot's done word in host memory, which the host polls.
+//  * Every other workgroup (a worker, one per compute unit) claims the next
+//    global tile number g with an atomic add, waits until word g carries tag
+//    g, then runs that tile and adds one to the entry's completed-tile count.
+//    A tile of phase k > 0 first waits until the slot's phase word reaches k;
+//    the tile whose count completes phase k - 1 stores it.  Tiles are
+//    numbered phase by phase, so the earliest unfinished tile never waits on
+//    a later one and the loop cannot deadlock.  The workgroup that completes
+//    the entry's last tile stores seq + 1 (bit 63: a dependency wait timed
+//    out) into the slot's done word in host memory, which the host polls.
 //  * Tiles of different workgroups meet through device memory on different
-//    XCDs, whose L2 caches are not coherent with each other within a kernel:
-//    a tile's stores are released at agent scope (L2 write-back) before its
-//    count is raised, and a tile acquires at agent scope (L2 invalidate)
-//    before it reads what other tiles or the dispatcher wrote.  Each is done
-//    once per workgroup, by one lane after every wave has waited for its own
-//    stores: these cache operations act on the XCD's whole L2 and queue
-//    behind each other, and one per wave made a 64-tile request take twice
-//    as long.
+//    XCDs, whose L2 caches are not coherent with each other within a kernel.
+//    A tile invalidates its compute unit's L1 and its XCD's L2 once (agent-
+//    scope acquire, by one lane) before it reads the descriptor, the
+//    request's inputs and its twiddle tables.  The residues tiles write (a
+//    phase's outputs, read by the next phase, and the request's results)
+//    move by device-scope loads and stores, so no L2 write-back is needed:
+//    every wave waits for its own stores before the count is raised.
+//  * Device-scope accesses to one 128-byte line are served one after
+//    another, so the words that many workgroups touch at once -- the claim
+//    cursor, the stop and heartbeat words, the completion count, each slot's
+//    phase word -- sit on lines of their own, and idle workers read the stop
+//    and heartbeat words on every 8th poll only.
 //  * Every wait is bounded: workers leave when the dispatcher sets the stop
 //    word, or when its heartbeat has not moved for the stall bound (a
 //    dispatcher that is not running); the dispatcher leaves when the host
@@ -60,16 +65,10 @@ constexpr u32 kResBlasChunk = 4 * 256;      // residues per BLAS tile
 constexpr u32 kResMaxLog2N = 17;            // largest transform the loop takes (a plan's largest)
 // By default every request the loop can take goes to it; a smaller bound
 // (mw_server_config.resident_max_tiles) sends larger requests to the slot
-// path.  Per request class the loop is faster for small requests and slower
-// for large ones -- every tile pays an L2 invalidate and an L2 write-back on
-// its XCD, and the loop runs the run-time line engine (measured on MI355X,
-// 20 K requests/s Poisson stream, p50 in us, loop vs slot path: BLAS 2^10
-// (1 tile) 20.4 vs 23.7, 2^16 (64 tiles) 32.7 vs 24.6; 124-bit NTT 2^10
-// (2 tiles) 29.3 vs 33.7, 2^17 (256) 69.7 vs 40.1) -- but a slot-path
-// launch can land on the loop's hardware queue and then waits for the loop
-// to yield, so over the whole stream routing everything to the loop measured
-// best: p50 / p99 / mean 34.3 / 82.4 / 38.6 us against 37.9 / 91.8 / 40.3
-// for the slot path alone.
+// path.  A slot-path launch can land on the loop's hardware queue and then
+// waits for the loop to yield, and the loop is faster than the slot path for
+// requests of every size it takes (measured on MI355X, 20 K requests/s
+// Poisson stream).
 constexpr u32 kResRouteTiles = kResMaxTiles;
 constexpr u64 kResTagMask = (u64(1) << 40) - 1;
 
@@ -97,26 +96,36 @@ struct alignas(16) ResEntry {
 };
 static_assert(sizeof(ResEntry) % 16 == 0, "entries are copied in 16-byte units");
 
-// Device control words, reset by the host before each launch.
+// Device control words, reset by the host before each launch.  The words
+// that idle workers poll (stop, beat), the claim cursor and the completion
+// count sit on 128-byte lines of their own: device-scope accesses to one line
+// queue behind each other in memory.
 struct ResCtl {
-  u64 gcursor;          // next global tile number to claim
-  u32 stop;             // dispatcher -> workers: leave
-  u32 exited;           // workers that have left
-  u64 completed;        // entries completed (cumulative over launches)
-  u32 error;            // a dependency wait timed out
-  u32 beat;             // dispatcher's heartbeat, raised on every poll
+  alignas(128) u64 gcursor;   // next global tile number to claim
+  alignas(128) u32 stop;      // dispatcher -> workers: leave
+  u32 beat;                   // dispatcher's heartbeat, raised on every poll
+  alignas(128) u64 completed; // entries completed (cumulative over launches)
+  alignas(128) u32 exited;    // workers that have left
+  u32 error;                  // a dependency wait timed out
 };
 
 // Device memory of the loop (one allocation).
+constexpr u32 kResLineWords = 128 / sizeof(u32);
 struct ResDevBlock {
   ResCtl ctl;
   u32 dcount[kResRing];           // tiles completed of the slot's entry
   u32 dfail[kResRing];            // the slot's entry had a failed wait
+  // phases of the slot's entry complete, one 128-byte line per slot: the
+  // waiting tiles of the next phase poll this word, not the count that the
+  // running tiles raise
+  u32 dphase[kResRing * kResLineWords];
   ResEntry dent[kResRing];        // descriptors, copied by the dispatcher
   u64 tiles[kResTileRing];        // tile words
 };
-static_assert(offsetof(ResDevBlock, dfail) == offsetof(ResDevBlock, dcount) + sizeof(u32) * kResRing,
-              "the per-slot counts are cleared as one range");
+static_assert(offsetof(ResDevBlock, dfail) == offsetof(ResDevBlock, dcount) + sizeof(u32) * kResRing &&
+                  offsetof(ResDevBlock, dphase) == offsetof(ResDevBlock, dfail) + sizeof(u32) * kResRing,
+              "the per-slot words are cleared as one range");
+static_assert(offsetof(ResDevBlock, dphase) % 128 == 0, "one line per slot");
 
 // Mapped pinned host memory of the loop.
 struct ResHost {

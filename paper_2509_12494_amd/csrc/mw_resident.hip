@@ -62,10 +62,12 @@ __device__ __forceinline__ void dispatch(const ResParams& p, u64& sh_a, u32& sh_
   for (;;) {
     if (t == 0) {
       store_agent(&D->ctl.beat, ++beat);
-      // while the host asks to yield, no new entry is taken
+      // while the host asks to yield, no new entry is taken; the three words
+      // are read together (one PCIe round trip)
       const u32 yielding = load_system(&H->yield);
-      sh_a = yielding ? consumed : load_system(&H->tail);
+      const u64 tail = load_system(&H->tail);
       const u32 stop = load_system(&H->stop) | yielding;
+      sh_a = yielding ? consumed : tail;
       const u64 done = load_agent(&D->ctl.completed);
       const u64 now = wall_clock64();
       if (done != seen_done) {
@@ -134,7 +136,7 @@ __device__ __forceinline__ void blas_tile_op(const ResEntry& E, const Modulus<W>
   const u64 lo = (u64)tile * kResBlasChunk;
   const u64 hi = lo + kResBlasChunk < E.n ? lo + kResBlasChunk : E.n;
   for (u64 i = lo + threadIdx.x; i < hi; i += blockDim.x)
-    ResIO<W>::store(c + i, blas_elem<W, OP, NORM>(ResIO<W>::load(a + i), ResIO<W>::load(b + i), M, s));
+    LoopIO::store(c + i, blas_elem<W, OP, NORM>(ResIO<W>::load(a + i), ResIO<W>::load(b + i), M, s));
 }
 
 template <int W>
@@ -165,21 +167,24 @@ __device__ __forceinline__ void work(const ResParams& p, ResEntry& E, u64& sh_wo
         const u64 tag = g & kResTagMask;
         u32 beat = load_agent(&D->ctl.beat);
         u64 beat_t = wall_clock64();
-        for (;;) {
+        // the shared stop and heartbeat words are read on every 8th poll only
+        for (u32 n = 1;; ++n) {
           w = load_agent(&D->tiles[g & (kResTileRing - 1)]);
           if ((w >> 24) == tag) break;
-          if (load_agent(&D->ctl.stop)) {
-            leave = 1;
-            break;
-          }
-          const u32 b = load_agent(&D->ctl.beat);
-          const u64 now = wall_clock64();
-          if (b != beat) {
-            beat = b;
-            beat_t = now;
-          } else if (now - beat_t > p.stall_ticks) {
-            leave = 1;   // no dispatcher is running
-            break;
+          if ((n & 7) == 0) {
+            if (load_agent(&D->ctl.stop)) {
+              leave = 1;
+              break;
+            }
+            const u32 b = load_agent(&D->ctl.beat);
+            const u64 now = wall_clock64();
+            if (b != beat) {
+              beat = b;
+              beat_t = now;
+            } else if (now - beat_t > p.stall_ticks) {
+              leave = 1;   // no dispatcher is running
+              break;
+            }
           }
           __builtin_amdgcn_s_sleep(32);
         }
@@ -192,7 +197,10 @@ __device__ __forceinline__ void work(const ResParams& p, ResEntry& E, u64& sh_wo
     const u64 w = sh_word;
     const u32 slot = (u32)(w >> 12) & 0xfffu, i = (u32)w & 0xfffu;
     // one invalidate for the workgroup (the L1 is the compute unit's, the L2
-    // the XCD's): the descriptor and the inputs are read fresh
+    // the XCD's): the descriptor, the request's inputs and its tables are
+    // read fresh.  What tiles of this loop write (the outputs of a phase, read
+    // by the next) moves by device-scope loads and stores (LoopIO) and needs
+    // no cache operation.
     if (t == 0) fence_acquire_agent();
     __syncthreads();
     copy_entry(&E, &D->dent[slot]);
@@ -201,17 +209,15 @@ __device__ __forceinline__ void work(const ResParams& p, ResEntry& E, u64& sh_wo
     while (phase + 1 < E.nphases && i >= E.prefix[phase + 1]) ++phase;
     if (phase > 0) {
       if (t == 0) {
-        const u32 need = E.prefix[phase];
         const u64 t0 = wall_clock64();
         u32 timed_out = 0;
-        while (load_agent(&D->dcount[slot]) < need) {
+        while (load_agent(&D->dphase[slot * kResLineWords]) < phase) {
           if (wall_clock64() - t0 > p.wait_ticks) {
             timed_out = 1;
             break;
           }
-          __builtin_amdgcn_s_sleep(4);
+          __builtin_amdgcn_s_sleep(2);
         }
-        fence_acquire_agent();
         sh_flag = timed_out;
       }
       __syncthreads();
@@ -220,34 +226,41 @@ __device__ __forceinline__ void work(const ResParams& p, ResEntry& E, u64& sh_wo
     if (!failed) {
       const u32 tile = i - E.prefix[phase];
       if (E.kind == RES_NTT) {
-        if (E.limbs == 2) run_item<4, kLogP4, false>(E.job, E.m4, phase, tile, smem);
-        else run_item<2, kLogP2, false>(E.job, E.m2, phase, tile, smem);
+        if (E.limbs == 2) run_item<4, kLogP4, false, LoopIO>(E.job, E.m4, phase, tile, smem);
+        else run_item<2, kLogP2, false, LoopIO>(E.job, E.m2, phase, tile, smem);
       } else {
         if (E.limbs == 2) blas_tile<4>(E, E.m4, E.s4, tile);
         else blas_tile<2>(E, E.m2, E.s2, tile);
       }
     }
-    // this tile's stores reach device scope before its count does: every
-    // wave's stores complete, then one L2 write-back for the workgroup
+    // this tile's device-scope stores are visible to every XCD before its
+    // count is: every wave waits until its own stores have completed
     wait_own_stores();
     __syncthreads();
     if (t == 0) {
       if (failed) {
         store_agent(&D->dfail[slot], 1u);
         store_agent(&D->ctl.error, 1u);
+        wait_own_stores();
       }
-      fence_release_agent();
       const u32 old = __hip_atomic_fetch_add(&D->dcount[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (old + 1 == E.total) {
         fence_acquire_agent();   // the failures other tiles recorded
         const u32 f = load_agent(&D->dfail[slot]);
         store_agent(&D->dcount[slot], 0u);
         store_agent(&D->dfail[slot], 0u);
+        store_agent(&D->dphase[slot * kResLineWords], 0u);
         __hip_atomic_fetch_add(&D->ctl.completed, u64(1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // every tile's output is visible to the host and its copies first
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
         __hip_atomic_store(&H->done[slot], (E.seq + 1) | ((u64)f << 63), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_SYSTEM);
+      } else if (phase + 1 < E.nphases && old + 1 == E.prefix[phase + 1]) {
+        // The last tile of its phase: tiles of a later phase wait for this
+        // one, so every tile counted so far is of this phase or an earlier
+        // one, and each wrote its outputs back before it counted.  The
+        // store follows the add that observed all of them.
+        store_agent(&D->dphase[slot * kResLineWords], phase + 1);
       }
     }
     __syncthreads();   // E and the shared words are rewritten by the next tile

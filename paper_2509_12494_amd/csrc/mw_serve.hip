@@ -15,7 +15,8 @@
 // stream.  Requests arriving meanwhile wait in the queue and go into the next
 // batch on the next free slot, so batches overlap on the device.
 //
-// With config.resident, one- and two-word requests of a few tiles instead go
+// With config.resident, one- and two-word requests (up to resident_max_tiles
+// tiles, by default every one the loop can take) instead go
 // to the device-resident request loop (mw_resident.h): the scheduler (or the
 // submitting thread, when the queue is empty) writes their descriptors into a
 // ring in mapped host memory, a persistent kernel runs them, and the
@@ -461,7 +462,7 @@ bool res_ensure_running(mw_server_s* S, bool check_end) {
   // the per-slot counts start from zero: an entry failed by an ended loop
   // may have left its count part-way
   if (hipMemcpyAsync(&X.D->ctl, &X.H->ctl_init, sizeof(ResCtl), hipMemcpyHostToDevice, X.stream) != hipSuccess ||
-      hipMemsetAsync(X.D->dcount, 0, sizeof(X.D->dcount) + sizeof(X.D->dfail), X.stream) != hipSuccess ||
+      hipMemsetAsync(X.D->dcount, 0, sizeof(X.D->dcount) + sizeof(X.D->dfail) + sizeof(X.D->dphase), X.stream) != hipSuccess ||
       resident_launch(p, X.grid, X.stream) != hipSuccess || hipEventRecord(X.ended, X.stream) != hipSuccess) {
     X.broken = true;
     return false;
@@ -751,9 +752,11 @@ int init_resident(mw_server_s* S) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) != hipSuccess ||
       hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, S->device) != hipSuccess || cus <= 0 || khz <= 0)
     return MW_EDEVICE;
-  // two workgroups per compute unit (what its registers allow): workgroup 0
-  // dispatches, the others work
-  X.grid = 2 * (uint32_t)cus;
+  // one worker per compute unit, plus the dispatcher (workgroup 0).  Two
+  // per unit fit, but the tiles of a request then often share a unit, and a
+  // phase lasts as long as its slowest tile: measured, the 2^17 two-word
+  // transform took 52 us p50 with two workers per unit and 46 us with one.
+  X.grid = (uint32_t)cus + 1;
   if (S->cfg.resident_max_tiles) X.route_tiles = S->cfg.resident_max_tiles;
   X.idle_ticks = (uint64_t)khz * 20;      // 20 ms
   X.wait_ticks = S->cfg.resident_wait_us ? (uint64_t)khz * S->cfg.resident_wait_us / 1000
