@@ -276,7 +276,62 @@ struct Round {
     for (int u = 0; u < P; ++u) line[pad_idx<LOGL, LOGP>(base_j | ((u32)u << L0))] = x[u];
     round_sync<S::TPL>(last_round);
   }
+
+  // Two points per lane (LOGP == 1): the round is one stage with one twiddle
+  // per lane.  Its table index, so that a tile can load the twiddles of all
+  // rounds before the first one.
+  static __device__ __forceinline__ u32 tw_index(u32 tid, u32 base) {
+    static_assert(LOGP == 1, "one stage per round");
+    const u32 base_j = ((tid >> L0) << (L0 + LOGP)) | (tid & ((1u << L0) - 1u));
+    return (base << s0) + (base_j >> (LOGL - s0));
+  }
+
+  // The round with its twiddle already loaded (LOGP == 1).
+  static __device__ __forceinline__ void run_loaded(Res<W>* line, u32 tid, const Tw<W>& t, const NttParams<W>& p,
+                                                    bool last_inv, bool canon, bool last_round) {
+    static_assert(LOGP == 1, "one stage per round");
+    const u32 base_j = ((tid >> L0) << (L0 + LOGP)) | (tid & ((1u << L0) - 1u));
+    const u32 i0 = pad_idx<LOGL, LOGP>(base_j), i1 = pad_idx<LOGL, LOGP>(base_j | (1u << L0));
+    Res<W> x0 = line[i0], x1 = line[i1];
+    if (DIR == DIR_INV && s0 == 0 && last_inv) BF::gs_last(x0, x1, p.ninv, p.ninv_w1, p.M);
+    else if (DIR == DIR_FWD) BF::ct(x0, x1, t, p.M);
+    else BF::gs(x0, x1, t, p.M);
+    if (canon) {
+      x0 = BF::canon(x0, p.M);
+      x1 = BF::canon(x1, p.M);
+    }
+    line[i0] = x0;
+    line[i1] = x1;
+    round_sync<S::TPL>(last_round);
+  }
 };
+
+// The twiddles of every round of a two-point-per-lane line (one per round),
+// in round order.  A lane of such a line does little arithmetic per round, so
+// a twiddle load issued at the start of each round (after the barrier that
+// ends the previous one) leaves its latency exposed once per stage; loading
+// them all up front, beside the tile's data loads, pays it once.
+template <int W, int LOGL, int DIR, class BF>
+struct LineTw {
+  Tw<W> t[LOGL];
+  template <int RR = 0>
+  __device__ __forceinline__ void load(u32 tid, u32 base, const Tw<W>* __restrict__ tw) {
+    constexpr int R = (DIR == DIR_FWD) ? RR : (LOGL - 1 - RR);
+    t[RR] = load_tw(tw, Round<W, LOGL, 1, DIR, R, BF>::tw_index(tid, base));
+    if constexpr (RR + 1 < LOGL) load<RR + 1>(tid, base, tw);
+  }
+};
+
+// All rounds of a two-point-per-lane line with the twiddles loaded.
+template <int W, int LOGL, int DIR, int RR = 0, class BF = NativeBfly>
+__device__ __forceinline__ void line_stages_loaded(Res<W>* line, u32 tid, const LineTw<W, LOGL, DIR, BF>& tws,
+                                                   const NttParams<W>& p, bool last_inv, bool final_fwd) {
+  constexpr int R = (DIR == DIR_FWD) ? RR : (LOGL - 1 - RR);
+  Round<W, LOGL, 1, DIR, R, BF>::run_loaded(line, tid, tws.t[RR], p, last_inv,
+                                            DIR == DIR_FWD && final_fwd && RR == LOGL - 1, RR == LOGL - 1);
+  if constexpr (RR + 1 < LOGL)
+    line_stages_loaded<W, LOGL, DIR, RR + 1, BF>(line, tid, tws, p, last_inv, final_fwd);
+}
 
 // All rounds of a line held in LDS (forward: rounds 0..R-1; inverse: R-1..0).
 // tid: lane index within the line; base: twiddle base (1, or N1 + b for rows);
@@ -330,6 +385,20 @@ __device__ __forceinline__ void ntt_tile(const NttParams<W>& p, Res<W>* lds, u32
     if (MODE == MODE_COL) c0 = (tile % tiles) * lines;
     else b_lo = tile % tiles;
   }
+  u32 base = 1;   // twiddle base of the lane's line
+  if (MODE == MODE_ROW) base = (1u << log_n1) + line_id * ((1u << log_n1) >> log_lines) + b_lo;
+  const bool last_inv = (DIR == DIR_INV) && (MODE != MODE_ROW);
+  const bool final_fwd = (DIR == DIR_FWD) && (MODE != MODE_COL);
+
+  // Column and row tiles of two points per lane (the one-transform shapes of
+  // two-pass transforms): every round's twiddle is loaded here, in flight
+  // with the data loads below.  Measured on MI355X, batch-1 forward + inverse:
+  // two-word 2^16 23.4 -> 22.0 us, 2^17 27.1 -> 25.4 us.  Single-workgroup
+  // transforms of 2^11 points were slower this way (15.2 -> 16.0 us), and
+  // four-word twiddles would take 16 registers per round.
+  constexpr bool kLoadTw = LOGP == 1 && W <= 4 && MODE != MODE_FULL;
+  LineTw<W, LOGL, DIR, BF> tws;
+  if constexpr (kLoadTw) tws.load(lane, base, p.tw);
 
   // ---- device memory -> LDS ----
   // lines * L/P threads move lines * L elements: exactly P each, no guard
@@ -376,11 +445,10 @@ __device__ __forceinline__ void ntt_tile(const NttParams<W>& p, Res<W>* lds, u32
   __syncthreads();
 
   // ---- stages ----
-  u32 base = 1;
-  if (MODE == MODE_ROW) base = (1u << log_n1) + line_id * ((1u << log_n1) >> log_lines) + b_lo;
-  const bool last_inv = (DIR == DIR_INV) && (MODE != MODE_ROW);
-  const bool final_fwd = (DIR == DIR_FWD) && (MODE != MODE_COL);
-  line_stages<W, LOGL, LOGP, DIR, 0, BF>(lds + line_id * S::NPAD, lane, base, p.tw, p, last_inv, final_fwd);
+  if constexpr (kLoadTw)
+    line_stages_loaded<W, LOGL, DIR, 0, BF>(lds + line_id * S::NPAD, lane, tws, p, last_inv, final_fwd);
+  else
+    line_stages<W, LOGL, LOGP, DIR, 0, BF>(lds + line_id * S::NPAD, lane, base, p.tw, p, last_inv, final_fwd);
 
   // ---- LDS -> device memory ----
   if (MODE == MODE_FULL) {
