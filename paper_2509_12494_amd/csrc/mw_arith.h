@@ -64,7 +64,8 @@ struct Modulus {
   u32 mu[W];   // Barrett mu = floor(2^(2(32W-4)) / q') (32W-3 bits)
   u32 bits;    // b = bitlen(q)
   u32 shift;   // (32W - 4) - b
-  u32 pad_[2];
+  u32 est_rcp; // bits of a float just below 1 / (q_top + 1), q_top = q's top word
+  u32 est_ok;  // 1: q_top >= 2^16, so canon16 may estimate the quotient from it
 };
 
 // Bit length of a normalised Barrett modulus of W words.

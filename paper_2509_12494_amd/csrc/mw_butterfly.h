@@ -54,8 +54,31 @@ __device__ __forceinline__ void gs_bfly_last(Res<W>& X, Res<W>& Y, const Tw<W>& 
   Y = y;
 }
 
+// Canonical x mod q for x in [0, 16q).
+// When q's top word q_top has at least 17 bits (M.est_ok), the quotient
+// k = floor(x / q) <= 15 is estimated from x's top word t:
+// k' = trunc(float(t) * r), with r < 1 / (q_top + 1) (set_quotient_estimate).
+// - k' <= t / (q_top + 1) <= x / q, so k' <= k.
+// - x / q - t / (q_top + 1) < 17 / q_top <= 2^-11.9, and the float roundings
+//   lose less than 2^-15, so k <= k' + 1.
+// Then x - k'q is in [0, 2q), and one conditional subtraction of q ends it:
+// 19 word instructions for two words instead of the 32 of four conditional
+// subtractions (8q, 4q, 2q, q), which remain for smaller moduli.
 template <int W>
 __device__ __forceinline__ Res<W> canon16(const Res<W>& x, const Modulus<W>& M) {
+  if (M.est_ok) {
+    const u32 k = (u32)((float)x.v[W - 1] * __builtin_bit_cast(float, M.est_rcp));
+    u32 kq[W];
+    u64 c = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      const u64 t = mad(k, M.q[i], c);   // k < 16: no overflow, and k q < 2^(32W)
+      kq[i] = (u32)t;
+      c = t >> 32;
+    }
+    u32 borrow;
+    return csub(sub(x, kq, borrow), M.q);
+  }
   return csub(csub(csub(csub(x, M.q8), M.q4), M.q2), M.q);
 }
 

@@ -37,6 +37,17 @@ inline void put_words(mwhost::u128 v, u32 (&out)[W]) {
   for (int i = 0; i < W; ++i) out[i] = (u32)(v >> (32 * i));
 }
 
+// The reciprocal canon16 estimates a quotient with: r = (1 - 2^-20) / (q_top + 1)
+// in double, rounded to float (at most 2^-24 up), so r < 1 / (q_top + 1).
+// Used when q's top word q_top has at least 17 bits.
+template <int W>
+inline void set_quotient_estimate(Modulus<W>& M) {
+  const u32 top = M.q[W - 1];
+  M.est_ok = top >= (1u << 16) ? 1u : 0u;
+  const float r = (float)((1.0 - 1.0 / (1 << 20)) / ((double)top + 1.0));
+  M.est_rcp = M.est_ok ? __builtin_bit_cast(u32, r) : 0u;
+}
+
 template <int W>
 inline void make_modulus(const uint64_t* q, uint32_t limbs, Modulus<W>& M) {
   mwhost::u128 Q = mwhost::from_words(q, limbs);
@@ -54,7 +65,7 @@ inline void make_modulus(const uint64_t* q, uint32_t limbs, Modulus<W>& M) {
   put_words<W>(mwhost::pow2_div(2 * T, Qn), M.mu);
   M.bits = (u32)b;
   M.shift = (u32)(T - b);
-  M.pad_[0] = M.pad_[1] = 0;
+  set_quotient_estimate(M);
 }
 
 template <int W>
@@ -78,7 +89,7 @@ inline void make_modulus(const uint64_t* q, Modulus<8>& M) {
   put_words<8>(mwhost::pow2_div(2 * T, Qn), M.mu);
   M.bits = (u32)b;
   M.shift = (u32)(T - b);
-  M.pad_[0] = M.pad_[1] = 0;
+  set_quotient_estimate(M);
 }
 
 inline int make_scalar(const uint64_t* w, const uint64_t* q, u32 (&wv)[8], u32 (&ws)[8]) {

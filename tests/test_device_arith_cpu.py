@@ -153,3 +153,53 @@ def test_emulation_detects_a_planted_error(emulator, tmp_path):
         want.append((x * w) % q)
     got = _run(exe, lines)
     assert any(g[0] % q != v or g[0] >= 6 * q for g, v in zip(got, want))
+
+
+@pytest.mark.parametrize("words", [2, 4, 8])
+def test_canonicalisation_around_every_multiple(emulator, words):
+    """canon16 from [0, 16q) to [0, q): x = kq - 1, kq, kq + 1 for every k in
+    1..15, the ends of the range and random values, for moduli whose top word
+    is just below and at 2^16 (the quotient estimate's threshold), well inside
+    and at the top of the width class (bit length 32 W - 4)."""
+    rnd = random.Random(77 + words)
+    base = 32 * (words - 1)
+    moduli = [
+        (((1 << 16) - 1) << base) | 1 | (rnd.getrandbits(base) | 1),   # top word 2^16 - 1: four subtractions
+        ((1 << 16) << base) | 1,                                        # top word 2^16: the estimate, smallest
+        ((1 << 16) << base) | (rnd.getrandbits(base) | 1),
+        (rnd.randrange(1 << 20, 1 << 27) << base) | (rnd.getrandbits(base) | 1),
+        (1 << (32 * words - 4)) - 1,                                    # largest odd modulus of the class
+        ((1 << 27) << base) | 1,                                        # smallest with a full top word
+    ]
+    for q in moduli:
+        assert q % 2 == 1 and q.bit_length() <= 32 * words - 4
+        xs = {0, 1, q - 1, 16 * q - 1, 16 * q - 2}
+        for k in range(1, 16):
+            xs |= {k * q - 1, k * q, k * q + 1}
+        xs = sorted(x for x in xs if 0 <= x < 16 * q) + [rnd.randrange(16 * q) for _ in range(300)]
+        lines = [f"canon {words} {_h(q)} {_h(x)}" for x in xs]
+        got = _run(emulator, lines)
+        bad = [(hex(x), g) for x, g in zip(xs, got) if g[0] != x % q]
+        assert not bad, f"{len(bad)} of {len(xs)} wrong for q = {hex(q)}, first: {bad[0]}"
+
+
+def test_canonicalisation_detects_a_planted_error(tmp_path):
+    """The canonicalisation pin is able to fail: a copy whose quotient-estimate
+    reciprocal is rounded up instead of down gives wrong results just below
+    the multiples of q."""
+    src = os.path.join(ROOT, "paper_2509_12494_amd", "csrc")
+    work = tmp_path / "pkg" / "csrc"
+    shutil.copytree(src, work)
+    shutil.copytree(os.path.join(ROOT, "include"), tmp_path / "include")
+    text = (work / "mw_common.h").read_text()
+    needle = "(1.0 - 1.0 / (1 << 20))"
+    assert needle in text
+    (work / "mw_common.h").write_text(text.replace(needle, "(1.0 + 1.0 / (1 << 10))"))
+    exe = str(tmp_path / "emulate_bad")
+    cxx = CLANG if os.path.exists(CLANG) else shutil.which("clang++")
+    subprocess.run([cxx, "-O2", "-std=c++17", "-I" + os.path.join(HERE, "stub"), "-I" + str(work),
+                    "-I" + os.path.join(ROOT, "include"), os.path.join(HERE, "emulate.cpp"), "-o", exe], check=True)
+    q = W.find_prime(124, 1425)
+    xs = [k * q - d for k in range(1, 16) for d in (1, 2, 1 << 20)]
+    got = _run(exe, [f"canon 4 {_h(q)} {_h(x)}" for x in xs])
+    assert any(g[0] != x % q for g, x in zip(got, xs))
