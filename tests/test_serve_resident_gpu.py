@@ -6,8 +6,9 @@ through the plain entry points (and the oracle on sampled outputs): in a
 burst with the default routing and with every request in the loop, one
 request at a time (N = 2^6 .. 2^17, widths inside each class), mixed with
 four-word requests that keep the slot path, at the largest product (2^17,
-124-bit) and after the loop has left on idling and been launched again.  The
-routing follows the tile counts."""
+124-bit) and after the loop has left on idling and been launched again, and
+with inputs rewritten and plans replaced between requests.  The routing
+follows the tile counts."""
 import time
 
 import pytest
@@ -233,3 +234,44 @@ def test_resident_validate_mode_keeps_slot_path():
         mwntt.set_validate(prev)
     for p in plans.values():
         p.destroy()
+
+
+def test_resident_rewritten_inputs_and_replaced_plans():
+    """Device memory that changes while the loop runs: one input buffer is
+    rewritten (a device copy, completed before each submit) between requests,
+    and plans are destroyed and created again with other moduli, whose tables
+    may land at the addresses of the old ones.  Each result follows the new
+    contents: a tile reads its inputs and tables after an L2 invalidate on its
+    XCD, and what earlier phases wrote with device-scope loads.  Transforms of
+    2^16 (two phases, 256 tiles) and 2^12, and vec_mulmod of 2^16 residues."""
+    require_gpu()
+    import torch
+    from paper_2509_12494_amd import workloads as W
+    n = 1 << 16
+    srv = mwntt.MwServer(1 << 30, max_inflight=2, max_batch=8, resident=True, resident_max_tiles=4096)
+    announce("resident: rewritten inputs, replaced plans")
+    for rep in range(6):
+        q = W.find_prime(124, 600 + rep)
+        g = W.rng(600 + rep)
+        plans = {16: mwntt.ntt_plan(16, q, 2), 12: mwntt.ntt_plan(12, q, 2)}
+        a = mwntt.to_device(W.uniform_residues(g, q, n, 2))
+        b = mwntt.to_device(W.uniform_residues(g, q, n, 2))
+        for k in range(3):
+            # new contents in the same buffer for each request
+            a.copy_(mwntt.to_device(W.uniform_residues(g, q, n, 2)))
+            torch.cuda.synchronize()
+            items = [dict(op=mwntt.MW_REQ_NTT_FORWARD, q=q, limbs=2, n=n, plan=plans[16], a=a, b=None, alpha=0),
+                     dict(op=mwntt.MW_REQ_NTT_INVERSE, q=q, limbs=2, n=1 << 12, plan=plans[12],
+                          a=a[:1 << 12], b=None, alpha=0),
+                     dict(op=mwntt.MW_REQ_VEC_MULMOD, q=q, limbs=2, n=n, plan=None, a=a, b=b, alpha=0)]
+            for it in items:
+                t = srv.submit(_request(it))
+                ptr, lat = srv.result(t, wait=True)
+                out = mwntt.copy_to_tensor(ptr, it["a"])
+                torch.cuda.synchronize()
+                srv.release(t)
+                assert torch.equal(out, _alone(it)), f"rep {rep} request {k} op {it['op']}"
+        for p in plans.values():
+            p.destroy()
+    assert srv.stats()["resident_requests"] == 6 * 3 * 3
+    srv.destroy()
